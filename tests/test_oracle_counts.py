@@ -1,0 +1,283 @@
+"""Pins of the oracle's counting side (normalisation, reindex, the
+restricted nested-loop enumeration and its byte instrumentation) against
+brute force, closed forms and identities that hold for any graph."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from oracle import patterns as P
+from paper_1911_12877_amd import synth
+
+
+def _graphs_tiny():
+    yield "er14a", synth.er_edges(14, 0.45, 1)
+    yield "er16b", synth.er_edges(16, 0.30, 2)
+    s, d, n = synth.rmat_edges(4, 6, seed=3)
+    yield "rmat4", (s, d, n)
+    yield "cl", synth.chung_lu_edges(18, 2.3, 6.0, 4, cap=False)
+
+
+# ------------------------------------------------------------ graph prep
+
+
+def test_normalize_invariants():
+    s, d, n = synth.rmat_edges(10, 8, seed=7)
+    rowptr, col = oracle.normalize(s, d, n)
+    pairs = set()
+    for u, v in zip(s.tolist(), d.tolist()):
+        if u != v:
+            pairs.add((min(u, v), max(u, v)))
+    assert col.shape[0] == 2 * len(pairs)
+    for v in range(n):
+        row = col[rowptr[v]:rowptr[v + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert not np.any(row == v)
+    A = brute.dense_adjacency(s, d, n)
+    B = np.zeros_like(A)
+    for v in range(n):
+        B[v, col[rowptr[v]:rowptr[v + 1]]] = True
+    assert np.array_equal(A, B)
+
+
+def test_reindex_is_degree_order_and_isomorphic():
+    s, d, n = synth.rmat_edges(9, 8, seed=11)
+    rowptr, col = oracle.normalize(s, d, n)
+    r2, c2, perm = oracle.reindex(rowptr, col)
+    deg_old = np.diff(rowptr)
+    deg_new = np.diff(r2)
+    assert np.all(np.diff(deg_new) <= 0)                    # non-increasing
+    assert np.array_equal(deg_new[perm], deg_old)
+    ties = [v for v in range(n - 1) if deg_new[v] == deg_new[v + 1]]
+    old_of_new = np.argsort(perm)
+    assert all(old_of_new[v] < old_of_new[v + 1] for v in ties)
+    for v in range(n):                                      # edge-preserving
+        mapped = np.sort(perm[col[rowptr[v]:rowptr[v + 1]]])
+        assert np.array_equal(mapped, c2[r2[perm[v]]:r2[perm[v] + 1]])
+
+
+def test_star_orientation(golden):
+    """Section 6: the hub gets id 0 and has no lower-id neighbour."""
+    g = oracle.from_edge_tuple(synth.star_edges(9))
+    lo = oracle.lo_end(g)
+    assert g.new_of_old[0] == 0
+    assert lo[0] == golden["star_orientation"]["hub_lower_neighbours"]
+    assert lo.sum() == g.col.shape[0] // 2
+
+
+# ------------------------------------------------- brute force vs oracle
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+@pytest.mark.parametrize("induced", [True, False])
+def test_oracle_matches_bruteforce(k, induced):
+    for name, e in _graphs_tiny():
+        A = brute.dense_adjacency(*e)
+        g = oracle.from_edge_tuple(e)
+        for pat in P.connected_patterns(k):
+            want = brute.count(A, pat, induced)
+            assert oracle.count(g, pat, induced) == want, (name, pat)
+
+
+@pytest.mark.parametrize("name", ["k6e", "c6chord03", "c6chord02", "k6", "c6",
+                                  "k7e", "house"])
+def test_oracle_matches_bruteforce_larger_patterns(name):
+    pat = P.named(name)
+    for seed, p in ((5, 0.6), (6, 0.75)):
+        e = synth.er_edges(11, p, seed)
+        A = brute.dense_adjacency(*e)
+        g = oracle.from_edge_tuple(e)
+        for induced in (True, False):
+            assert oracle.count(g, pat, induced) == brute.count(A, pat, induced)
+
+
+def test_bruteforce_closed_forms():
+    """The brute force itself against textbook counts."""
+    K = brute.dense_adjacency(*synth.complete_edges(7))
+    for k in (3, 4, 5):
+        assert brute.count(K, P.named(f"k{k}")) == math.comb(7, k)
+    for k in (4, 5):
+        assert brute.count(K, P.named(f"c{k}")) == 0
+        assert brute.count(K, P.named(f"c{k}"), induced=False) == \
+            math.perm(7, k) // (2 * k)
+    B = brute.dense_adjacency(*synth.complete_bipartite_edges(4, 5))
+    assert brute.count(B, P.named("c4")) == math.comb(4, 2) * math.comb(5, 2)
+    assert brute.count(B, P.named("triangle")) == 0
+    Pe = brute.dense_adjacency(*synth.petersen_edges())
+    assert brute.count(Pe, P.named("c5")) == 12
+    assert brute.count(Pe, P.named("c4")) == 0
+
+
+# ------------------------------------------------------------ closed forms
+
+
+@pytest.mark.parametrize("n", [9, 12])
+def test_complete_graph_closed_forms(n):
+    g = oracle.from_edge_tuple(synth.complete_edges(n))
+    for k in (3, 4, 5, 6):
+        assert oracle.count(g, P.named(f"k{k}")) == math.comb(n, k)
+    for name in ["c4", "diamond", "tailed_triangle", "house", "k5e", "c6chord03"]:
+        pat = P.named(name)
+        k = len(pat)
+        assert oracle.count(g, pat, True) == 0
+        assert oracle.count(g, pat, False) == math.perm(n, k) // P.multiplicity(pat)
+
+
+def test_structured_graph_closed_forms():
+    g = oracle.from_edge_tuple(synth.complete_bipartite_edges(6, 7))
+    assert oracle.count(g, P.named("c4")) == math.comb(6, 2) * math.comb(7, 2)
+    assert oracle.count(g, P.named("triangle")) == 0
+    g = oracle.from_edge_tuple(synth.petersen_edges())
+    assert oracle.count(g, P.named("c5")) == 12
+    assert oracle.count(g, P.named("triangle")) == 0
+    assert oracle.count(g, P.named("c4")) == 0
+    for d in (5, 8):
+        g = oracle.from_edge_tuple(synth.star_edges(d))
+        for k in (3, 4, 5):
+            assert oracle.count(g, P.named(f"star{k}")) == math.comb(d, k - 1)
+    for n in (9, 13):
+        g = oracle.from_edge_tuple(synth.cycle_edges(n))
+        for k in (3, 4, 5, 6):
+            assert oracle.count(g, P.named(f"p{k}")) == n
+    for d in (3, 4, 5):
+        g = oracle.from_edge_tuple(synth.hypercube_edges(d))
+        assert oracle.count(g, P.named("c4")) == math.comb(d, 2) * 2 ** (d - 2)
+
+
+def test_triangles_trace_identity():
+    """Triangles = trace(A^3) / 6 on the 2000-vertex uniform workload."""
+    e = synth.config_graph("er2000")
+    A = brute.dense_adjacency(*e).astype(np.float64)
+    want = int(round(np.trace(A @ A @ A) / 6.0))
+    g = oracle.from_edge_tuple(e)
+    assert oracle.count(g, P.named("triangle")) == want
+
+
+def _four_vertex_identities(e):
+    """Non-induced 4-vertex counts from degrees, triangles and common
+    neighbours; returns dict of closed-form values."""
+    src, dst, n = e
+    A = brute.dense_adjacency(src, dst, n).astype(np.int64)
+    d = A.sum(1)
+    A2 = A @ A
+    t_edge = A2 * A                      # triangles through each edge
+    t_v = np.diag(A2 @ A) // 2           # triangles through each vertex
+    T = int(np.trace(A2 @ A)) // 6
+    iu = np.triu_indices(n, 1)
+    E_u, E_v = np.nonzero(np.triu(A, 1))
+    out = {}
+    out["star4"] = int(sum(math.comb(int(x), 3) for x in d))
+    out["p4"] = int(np.sum((d[E_u] - 1) * (d[E_v] - 1))) - 3 * T
+    out["tailed_triangle"] = int(np.sum(t_v * (d - 2)))
+    c = A2[iu]
+    out["c4"] = int(np.sum(c * (c - 1) // 2)) // 2
+    te = t_edge[E_u, E_v]
+    out["diamond"] = int(np.sum(te * (te - 1) // 2))
+    return out
+
+
+@pytest.mark.parametrize("which", ["er", "cl"])
+def test_four_vertex_induced_identities(which):
+    if which == "er":
+        e = synth.er_edges(70, 0.18, 21)
+    else:
+        e = synth.chung_lu_edges(400, 2.3, 10.0, 22, cap=False)
+    g = oracle.from_edge_tuple(e)
+    I = {nm: oracle.count(g, P.named(nm), True)
+         for nm in ["c4", "diamond", "tailed_triangle", "p4", "star4", "k4"]}
+    N = {nm: oracle.count(g, P.named(nm), False)
+         for nm in ["c4", "diamond", "tailed_triangle", "p4", "star4"]}
+    cf = _four_vertex_identities(e)
+    for nm in cf:
+        assert N[nm] == cf[nm], nm
+    K4 = I["k4"]
+    assert N["c4"] == I["c4"] + I["diamond"] + 3 * K4
+    assert N["diamond"] == I["diamond"] + 6 * K4
+    assert N["tailed_triangle"] == I["tailed_triangle"] + 4 * I["diamond"] + 12 * K4
+    assert N["p4"] == I["p4"] + 2 * I["tailed_triangle"] + 4 * I["c4"] + \
+        6 * I["diamond"] + 12 * K4
+    assert N["star4"] == I["star4"] + I["tailed_triangle"] + 2 * I["diamond"] + 4 * K4
+
+
+def test_near_clique_identity():
+    """N(K5-e) = sum over triangles Q of C(|common nbrs of Q|, 2);
+    I(K5-e) = N(K5-e) - 10 * #K5."""
+    e = synth.er_edges(40, 0.45, 31)
+    src, dst, n = e
+    A = brute.dense_adjacency(src, dst, n)
+    nbr = [set(np.nonzero(A[v])[0].tolist()) for v in range(n)]
+    N = 0
+    for a in range(n):
+        for b in nbr[a]:
+            if b <= a:
+                continue
+            for c in nbr[a] & nbr[b]:
+                if c <= b:
+                    continue
+                N += math.comb(len(nbr[a] & nbr[b] & nbr[c]), 2)
+    g = oracle.from_edge_tuple(e)
+    assert oracle.count(g, P.named("k5e"), False) == N
+    assert oracle.count(g, P.named("k5e"), True) == N - 10 * oracle.count(g, P.named("k5"))
+
+
+# --------------------------------------------------------------- invariants
+
+
+@pytest.mark.parametrize("name", ["c4", "diamond", "tailed_triangle", "house",
+                                  "k5e", "c5", "p5"])
+def test_schedule_invariance_and_theorem1(name):
+    """Every distinct schedule gives the same count; the unrestricted count
+    is |Aut| times the restricted one (Theorem 1); Theorem 2's reduced
+    bounds give the same count as the full relation set."""
+    pat = P.named(name)
+    e = synth.chung_lu_edges(300, 2.2, 8.0, 41, cap=True)
+    g = oracle.from_edge_tuple(e)
+    aut = P.multiplicity(pat)
+    for induced in (True, False):
+        want = oracle.count(g, pat, induced)
+        for s in P.distinct_schedules(pat):
+            assert oracle.count(g, pat, induced, order=s) == want
+            assert oracle.count(g, pat, induced, order=s, relations="thm2") == want
+        assert oracle.count(g, pat, induced, relations="none") == aut * want
+
+
+def test_relabelling_invariance():
+    e = synth.er_edges(60, 0.2, 51)
+    src, dst, n = e
+    perm = np.random.Generator(np.random.PCG64(5)).permutation(n).astype(np.int32)
+    g1 = oracle.from_edge_tuple(e)
+    g2 = oracle.prepare(perm[src], perm[dst], n, reindex_by_degree=False)
+    for nm in ["c4", "diamond", "house", "k4"]:
+        assert oracle.count(g1, P.named(nm)) == oracle.count(g2, P.named(nm))
+
+
+def test_per_root_decomposition():
+    e = synth.chung_lu_edges(500, 2.4, 9.0, 61, cap=True)
+    g = oracle.from_edge_tuple(e)
+    pat = P.named("house")
+    s = P.pick_schedule(pat, True)[0]
+    total = oracle.count(g, pat, True, order=s)
+    roots = np.arange(g.n, dtype=np.int32)
+    t2, per = oracle.count(g, pat, True, order=s, roots=roots, per_root=True)
+    assert t2 == total == int(per.sum())
+
+
+def test_instrument_triangle_closed_form():
+    """Triangle, schedule (0,1,2), bounds v1<v0, v2<v1: level 1 reads the
+    lower part of N(v0) once per root; level 2 reads N(v0) and N(v1) below
+    v1 once per lower edge (v0, v1)."""
+    e = synth.chung_lu_edges(300, 2.3, 10.0, 71, cap=True)
+    g = oracle.from_edge_tuple(e)
+    lo = oracle.lo_end(g)
+    want = int(np.sum(4 * lo + 8))
+    for v0 in range(g.n):
+        row0 = g.col[g.rowptr[v0]:g.rowptr[v0 + 1]]
+        for v1 in row0[row0 < v0]:
+            want += 4 * int(np.sum(row0 < v1)) + 4 * int(lo[v1]) + 16
+    tri = P.named("triangle")
+    b, c = oracle.instrument(g, tri, True, (0, 1, 2), [-1, 0, 1])
+    assert b == want
+    assert c == oracle.count(g, tri)
