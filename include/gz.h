@@ -1,0 +1,219 @@
+/*
+ * gz.h - C-ABI of the MI355X (gfx950) exact subgraph-counting library.
+ *
+ * The method is GraphZero's (Mawhirter et al., "GraphZero: Breaking Symmetry
+ * for Efficient Graph Mining"): a pattern is compiled into a schedule (an
+ * order of its vertices, Section 2.1) plus one symmetry-breaking restriction
+ * per loop (Algorithm 1 and Theorem 2), the graph is reindexed so that higher
+ * degree means a smaller id (Section 6), and nested loops grow each embedding
+ * one vertex at a time by bounded intersections (pattern edges) and
+ * subtractions (pattern non-edges) of sorted neighbour lists.  Each instance
+ * is counted exactly once (Theorem 1).
+ *
+ * Conventions
+ *  - Every call returns gz_status: GZ_OK (0) or a negative error code; the
+ *    calling thread's last error message is available from gz_last_error().
+ *    No call aborts the process.
+ *  - Input arrays are owned by the caller and only read during the call
+ *    (host arrays, or device arrays with GZ_GRAPH_DEVICE_PTRS); nothing is
+ *    retained.  Output arrays are caller-provided host buffers.
+ *  - Handles are owned by the library until freed.  A graph handle owns its
+ *    device memory; both handle types are immutable after creation, so
+ *    concurrent gz_count calls on different streams are allowed.
+ *  - hip_stream is a hipStream_t (NULL = the default stream); device work of
+ *    a call is ordered on that stream and the call returns after it is done.
+ *  - Vertex ids are int32, neighbour-array offsets int32 (nnz < 2^31),
+ *    counts uint64.
+ */
+#ifndef GZ_H
+#define GZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gz_status;
+enum {
+    GZ_OK = 0,
+    GZ_EINVAL = -1,      /* bad argument, malformed graph or pattern          */
+    GZ_ENOMEM = -2,      /* host or device allocation failed                  */
+    GZ_EDEVICE = -3,     /* a HIP runtime call failed                          */
+    GZ_EOVERFLOW = -4,   /* the exact count does not fit in 64 bits            */
+    GZ_ENOTSUP = -5      /* supported by the interface, not by this build      */
+};
+
+typedef struct gz_graph gz_graph;
+typedef struct gz_schedule gz_schedule;
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Flags of gz_load_graph / gz_load_edges. */
+#define GZ_GRAPH_NORMALIZE   1u  /* drop self-loops and duplicates, symmetrise,
+                                    sort rows; without it the CSR must already
+                                    be simple, symmetric and sorted, else
+                                    GZ_EINVAL                                 */
+#define GZ_GRAPH_NO_REINDEX  2u  /* keep the caller's ids (orientation off);
+                                    counts are unchanged, only speed differs  */
+#define GZ_GRAPH_DEVICE_PTRS 4u  /* the input arrays are device pointers      */
+
+/*
+ * Load a graph given as CSR: rowptr[n+1] (rowptr[0] = 0, non-decreasing,
+ * rowptr[n] = nnz) and colidx[nnz] (neighbour ids in [0, n)).  The graph is
+ * undirected: each edge {u,v} appears in both rows.  Unless
+ * GZ_GRAPH_NO_REINDEX is given, vertices are renumbered by decreasing degree,
+ * ties by increasing id (Section 6, first technique); gz_graph_export returns
+ * the mapping.  The prepared graph (int32 CSR with ascending rows and, per
+ * vertex, the number of neighbours with a smaller id) is uploaded to the
+ * current HIP device.  Errors: GZ_EINVAL (n < 0, nnz out of range, malformed
+ * CSR), GZ_ENOMEM, GZ_EDEVICE.
+ */
+gz_status gz_load_graph(const int32_t* rowptr, const int32_t* colidx,
+                        int32_t n, int64_t nnz, uint32_t flags,
+                        void* hip_stream, gz_graph** out);
+
+/*
+ * Load a graph given as a raw edge list src[m], dst[m] over n vertices.  The
+ * list may hold self-loops, duplicates and one or both orientations of an
+ * edge; it is always normalised (GZ_GRAPH_NORMALIZE is implied).
+ */
+gz_status gz_load_edges(const int32_t* src, const int32_t* dst, int64_t m,
+                        int32_t n, uint32_t flags, void* hip_stream,
+                        gz_graph** out);
+
+/* Sizes of a prepared graph: vertices, stored neighbour entries (twice the
+ * edge count), largest degree, largest number of smaller-id neighbours. */
+gz_status gz_graph_info(const gz_graph* g, int32_t* n, int64_t* nnz,
+                        int32_t* max_deg, int32_t* max_lo_deg);
+
+/* Host copies of the prepared graph: rowptr[n+1], colidx[nnz] and
+ * old_of_new[n] (the caller's id of each prepared vertex).  Any pointer may
+ * be NULL to skip that array. */
+gz_status gz_graph_export(const gz_graph* g, int32_t* rowptr, int32_t* colidx,
+                          int32_t* old_of_new);
+
+void gz_free_graph(gz_graph* g);
+
+/*
+ * Host-only preparation (no device needed): the same normalisation and
+ * degree reindex as gz_load_edges, written to caller buffers.  rowptr_out
+ * needs n+1 entries, colidx_out 2*m (an upper bound of the result's nnz),
+ * old_of_new_out and lo_out n entries (lo_out[v]: number of neighbours of v
+ * with a smaller id).  *nnz_out receives the prepared nnz.  Any of
+ * old_of_new_out / lo_out may be NULL.  Errors: GZ_EINVAL for endpoints out
+ * of range or a result with 2^31 or more entries.
+ */
+gz_status gz_prepare_edges(const int32_t* src, const int32_t* dst, int64_t m,
+                           int32_t n, uint32_t flags, int64_t* nnz_out,
+                           int32_t* rowptr_out, int32_t* colidx_out,
+                           int32_t* old_of_new_out, int32_t* lo_out);
+
+/* ---------------------------------------------------------------- patterns */
+
+/* Flags of gz_compile_pattern / gz_compile_pattern_order. */
+#define GZ_SCHED_ANALYTIC    0u  /* pick the distinct schedule of lowest
+                                    analytic cost (Section 5.4)               */
+#define GZ_SCHED_NO_RESTRICT 8u  /* drop all restrictions: every automorphic
+                                    mapping is counted, so the result is
+                                    |Aut(P)| times the count (Theorem 1);
+                                    for tests                                 */
+
+/*
+ * Compile a pattern: adj is k*k row-major 0/1, symmetric, zero diagonal,
+ * connected, 2 <= k <= 8.  induced != 0 asks for vertex-induced counts (every
+ * pattern non-edge must be a graph non-edge, the set subtractions of
+ * Section 2.1); induced == 0 counts subgraphs (edge-induced).  Steps: the
+ * automorphism group by trying all k! permutations (Section 4.2); the
+ * distinct schedules by the explorer (Algorithm 3); per schedule the
+ * restrictions (Algorithm 1) reduced to one bound per loop (Theorem 2) and the
+ * analytic cost (Section 5.4, appendix); the cheapest schedule is lowered to
+ * per-loop descriptors.  Errors: GZ_EINVAL for a malformed or disconnected
+ * pattern or k out of range.
+ */
+gz_status gz_compile_pattern(const uint8_t* adj, int32_t k, int32_t induced,
+                             uint32_t flags, gz_schedule** out);
+
+/* Same with a caller-chosen schedule order[k] (a permutation of 0..k-1 in
+ * which every vertex after the first has an earlier neighbour).  GZ_EINVAL if
+ * the order is not a valid schedule. */
+gz_status gz_compile_pattern_order(const uint8_t* adj, int32_t k,
+                                   int32_t induced, const int8_t* order,
+                                   uint32_t flags, gz_schedule** out);
+
+/*
+ * Describe a compiled schedule.  order[8] receives the pattern vertex of each
+ * loop; bound[8] the loop whose vertex bounds loop i from above (the graph
+ * vertex of loop i must have a smaller id than that of loop bound[i]) or -1;
+ * aut_size |Aut(P)|; n_distinct the number of distinct schedules of the
+ * pattern; analytic_cost the cost of this schedule.  Any pointer may be NULL.
+ */
+gz_status gz_schedule_info(const gz_schedule* s, int8_t* order, int8_t* bound,
+                           uint64_t* aut_size, int32_t* n_distinct,
+                           double* analytic_cost);
+
+/*
+ * All distinct schedules of a pattern in the explorer's emission order
+ * (Algorithm 3): orders[max_orders*8] receives 8 entries per schedule (the
+ * first k used), costs[max_orders] their analytic costs (may be NULL).  At
+ * most max_orders are written; *n_total receives the full count.
+ */
+gz_status gz_enumerate_schedules(const uint8_t* adj, int32_t k,
+                                 int32_t induced, int8_t* orders,
+                                 double* costs, int32_t max_orders,
+                                 int32_t* n_total);
+
+void gz_free_schedule(gz_schedule* s);
+
+/* ---------------------------------------------------------------- counting */
+
+/*
+ * Exact number of instances of the compiled pattern in the graph (each
+ * instance once; |Aut(P)| times that with GZ_SCHED_NO_RESTRICT).  Runs the
+ * mining kernels on hip_stream and waits for them.  Errors: GZ_EINVAL (NULL
+ * handle), GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified),
+ * GZ_EDEVICE.
+ */
+gz_status gz_count(const gz_graph* g, const gz_schedule* s, void* hip_stream,
+                   uint64_t* out_count);
+
+/*
+ * gz_count that also reports the mining kernel's own duration in
+ * milliseconds, measured with HIP events recorded on hip_stream around that
+ * launch (accumulator set-up and the result copy are outside the interval).
+ */
+gz_status gz_count_timed(const gz_graph* g, const gz_schedule* s,
+                         void* hip_stream, uint64_t* out_count,
+                         float* kernel_ms);
+
+/*
+ * Per-root counts: out_per_root[i] receives the number of instances whose
+ * restricted mapping puts roots[i] (a prepared-graph id) in the first loop.
+ * Summed over all vertices these give gz_count.  Errors as gz_count, plus
+ * GZ_EINVAL for a root out of range.
+ */
+gz_status gz_count_roots(const gz_graph* g, const gz_schedule* s,
+                         const int32_t* roots, int64_t n_roots,
+                         void* hip_stream, uint64_t* out_per_root);
+
+/*
+ * Algorithmic bytes of one gz_count: over every evaluation of loops 1..k-1,
+ * 4 bytes per element of each neighbour list the loop's set expression
+ * reads (pattern-edge lists, plus pattern-non-edge lists when induced), cut
+ * at the loop's restriction bound (Section 6, second technique), plus 8 bytes
+ * per list for its row offsets.  Runs an instrumented (slower) pass; the
+ * count of that pass is returned too.
+ */
+gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
+                         void* hip_stream, uint64_t* out_bytes,
+                         uint64_t* out_count);
+
+/* ------------------------------------------------------------------ errors */
+
+const char* gz_last_error(void);
+const char* gz_status_string(gz_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GZ_H */

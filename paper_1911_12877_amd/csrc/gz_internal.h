@@ -1,0 +1,140 @@
+// Internal declarations shared by the host code (graph preparation, pattern
+// compiler, C-ABI) and the HIP mining kernels of libgz.
+#pragma once
+
+#include <stdint.h>
+
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gz.h"
+
+namespace gz {
+
+constexpr int kMaxK = 8;
+
+// ---------------------------------------------------------------- the plan
+//
+// Lowered schedule: one descriptor per loop i = 1..k-1 (loop 0 enumerates the
+// roots).  Bit j of a mask refers to loop j < i.
+//   isect : loops whose vertex is a pattern neighbour of loop i's vertex; the
+//           candidates lie in the intersection of their neighbour lists
+//   sub   : loops whose vertex is a pattern non-neighbour (vertex-induced mode
+//           only); their neighbour lists are subtracted
+//   excl  : loops whose graph vertex could equal a candidate and must be
+//           excluded explicitly (non-neighbours not already ruled out by the
+//           loop's bound chain)
+//   bound : the single kept restriction (Theorem 2): candidates must be
+//           smaller than the graph vertex of loop `bound`; -1 for none
+//   src   : an earlier materialised loop (2 <= src < i) whose candidate set
+//           already satisfies a subset of loop i's constraints and whose
+//           bound is no tighter; loop i may filter that set instead of
+//           intersecting lists; -1 when there is none
+//   pos_src / neg_src : isect / sub bits still to check when filtering src
+struct Level {
+  uint8_t isect;
+  uint8_t sub;
+  uint8_t excl;
+  int8_t bound;
+  int8_t src;
+  uint8_t pos_src;
+  uint8_t neg_src;
+  uint8_t pad;
+};
+
+struct Plan {
+  int32_t k;
+  int32_t induced;
+  Level lv[kMaxK];
+};
+
+// ---------------------------------------------------------------- patterns
+
+struct Pattern {
+  int k = 0;
+  uint8_t adj[kMaxK][kMaxK] = {};
+};
+
+using Perm = std::vector<int8_t>;  // x[v] = image of label v
+
+std::vector<Perm> automorphisms(const Pattern& p);
+bool pattern_connected(const Pattern& p);
+bool schedule_valid(const Pattern& p, const int8_t* order);
+std::vector<Perm> explore_schedules(const Pattern& p, const std::vector<Perm>& aut);
+void reduced_bounds(const Pattern& p, const std::vector<Perm>& aut,
+                    const int8_t* order, int8_t* bound);
+double analytic_cost(const Pattern& p, const int8_t* order, const int8_t* bound,
+                     bool induced);
+Plan lower_plan(const Pattern& p, const int8_t* order, const int8_t* bound,
+                bool induced);
+
+// ------------------------------------------------------------------ graphs
+
+struct HostGraph {
+  int32_t n = 0;
+  std::vector<int32_t> rowptr;      // n+1
+  std::vector<int32_t> col;         // nnz, ascending rows
+  std::vector<int32_t> lo;          // per vertex: neighbours with smaller id
+  std::vector<int32_t> old_of_new;  // n
+};
+
+// Build a simple symmetric graph from a raw edge list (self-loops and
+// duplicates dropped, rows sorted).  Returns false with a message on bad
+// input.
+bool graph_from_edges(const int32_t* src, const int32_t* dst, int64_t m,
+                      int32_t n, HostGraph* out, std::string* err);
+// Normalise an arbitrary CSR (same rules as above).
+bool graph_from_csr_normalize(const int32_t* rowptr, const int32_t* col,
+                              int32_t n, int64_t nnz, HostGraph* out,
+                              std::string* err);
+// Validate a CSR that must already be simple, symmetric and sorted.
+bool graph_from_csr_strict(const int32_t* rowptr, const int32_t* col, int32_t n,
+                           int64_t nnz, HostGraph* out, std::string* err);
+// Degree reindex: new ids by decreasing degree, ties by increasing old id.
+void graph_reindex(HostGraph* g);
+// Fill g->lo and the identity mapping where missing.
+void graph_finish(HostGraph* g);
+
+void parallel_for(int64_t n, int64_t grain,
+                  const std::function<void(int64_t, int64_t)>& body);
+
+// ---------------------------------------------------------------- handles
+
+// Task list of the first loop: root r contributes ceil(len1(r) / chunk)
+// tasks, each covering `chunk` consecutive first-loop candidates.
+struct DevTasks {
+  int64_t* prefix = nullptr;   // device, n_roots + 1 entries
+  int64_t n_tasks = 0;
+};
+
+void set_error(const std::string& msg);
+
+}  // namespace gz
+
+struct gz_graph {
+  gz::HostGraph host;
+  int32_t max_deg = 0;
+  int32_t max_lo = 0;
+  int device = 0;
+  int32_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  int32_t* d_lo = nullptr;
+  // first-loop task prefixes over all roots, by (bounded?, chunk) - built on
+  // first use and kept for the handle's life
+  mutable std::mutex task_mu;
+  mutable std::vector<std::pair<int64_t, gz::DevTasks>> task_cache;
+};
+
+struct gz_schedule {
+  gz::Pattern pat;
+  int induced = 1;
+  uint32_t flags = 0;
+  int8_t order[gz::kMaxK] = {};
+  int8_t bound[gz::kMaxK] = {};
+  uint64_t aut_size = 0;
+  int32_t n_distinct = 0;
+  double cost = 0.0;
+  gz::Plan plan{};
+};

@@ -1,0 +1,656 @@
+// HIP mining kernels for gfx950 (wave64): the nested loops of a compiled
+// schedule, run as a persistent wave-per-task depth-first search.
+//
+// Loop 0 enumerates roots v0.  Loop 1's candidates are a contiguous piece of
+// N(v0) (its first lo[v0] entries when loop 1 is bounded by v0: the
+// orientation prefix); the first-loop work of every root is cut into tasks of
+// `chunk` candidates and handed out through an atomic queue in vertex order
+// (decreasing degree after reindexing).  Loops 2..k-2 materialise their
+// candidate sets in LDS, `CH` base elements at a time; loop k-1 is only
+// counted.  A candidate set is the intersection of the neighbour lists of the
+// loop's pattern neighbours (Section 2.1), minus the lists of its pattern
+// non-neighbours in vertex-induced mode, cut at the loop's single restriction
+// bound (Theorem 2) - a prefix of every sorted list (Section 6, bounded set
+// operations).  Each set is evaluated from its shortest bounded operand; the
+// other operands are probed by binary search, and survivors are compacted
+// with ballot + mbcnt.  A loop may instead filter the materialised set of an
+// earlier loop whose constraints it contains (plan `src`).
+//
+// The last loop is flattened: the items of the enclosing loop's chunk are
+// laid out one per lane, their base lengths prefix-summed, and every lane
+// then takes one (item, base element) pair at a time, so short lists still
+// fill the wave.
+#include <hip/hip_runtime.h>
+
+#include "gz_internal.h"
+
+namespace gz {
+namespace dev {
+
+constexpr int WAVE = 64;
+constexpr int CH = 256;               // base elements per materialised chunk
+constexpr int BLOCK = 256;
+constexpr int WPB = BLOCK / WAVE;     // waves per workgroup
+constexpr int32_t INF = 0x7fffffff;
+constexpr int SRC_SLOT = 8;
+
+struct Graph {
+  const int32_t* __restrict__ rowptr;
+  const int32_t* __restrict__ col;
+  const int32_t* __restrict__ lo;
+  int32_t n;
+};
+
+struct Tasks {
+  const int64_t* __restrict__ prefix;  // n_roots + 1
+  const int32_t* __restrict__ roots;   // nullptr: root r is vertex r
+  int64_t n_roots;
+  int64_t n_tasks;
+  int32_t chunk;
+  int32_t bounded1;                    // loop 1 bounded by v0
+  int32_t batch;                       // tasks per queue pop
+  int32_t pad;
+};
+
+// acc[0..1]: 128-bit count; acc[2..3]: 128-bit bytes; acc[4]: queue head;
+// acc[5]: per-root overflow flag
+struct Out {
+  unsigned long long* acc;
+  unsigned long long* per_root;
+};
+
+template <int K>
+struct WaveMem {
+  static constexpr int NSET = K >= 4 ? K - 3 : 1;
+  int32_t set[NSET][CH];
+  int32_t set_len[NSET];
+  int32_t it_u[WAVE];
+  int32_t it_pref[WAVE];
+  int32_t it_bstart[WAVE];
+  int32_t it_slot[WAVE];
+  int32_t it_srclen[WAVE];
+  int32_t it_urs[WAVE];
+  int32_t it_urd[WAVE];
+};
+
+struct Acc {
+  unsigned long long cnt;
+  unsigned long long bytes;
+};
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int mbcnt(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ int32_t uni(int32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// first index in a[0..len) with a[i] >= x
+template <typename P>
+__device__ __forceinline__ int lower_bound(P a, int len, int32_t x) {
+  int lo = 0;
+  while (len > 0) {
+    int half = len >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+template <typename P>
+__device__ __forceinline__ bool contains(P a, int len, int32_t x) {
+  int i = lower_bound(a, len, x);
+  return i < len && a[i] == x;
+}
+
+// number of entries of the row (start, deg) below bound B; `own` when B is
+// the row's own vertex, whose smaller-id part has length lo
+__device__ __forceinline__ int bounded_len(const Graph& g, int32_t v, int32_t start,
+                                           int32_t deg, int32_t B, bool own) {
+  if (B == INF) return deg;
+  if (own) return g.lo[v];
+  return lower_bound(g.col + start, deg, B);
+}
+
+__device__ __forceinline__ int wave_excl_scan(int x, int* total) {
+  const int lane = lane_id();
+  int v = x;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    int y = __shfl_up(v, d, WAVE);
+    if (lane >= d) v += y;
+  }
+  *total = __shfl(v, WAVE - 1, WAVE);
+  return v - x;
+}
+
+// ------------------------------------------------------------ last loop
+
+template <int K, bool INSTR>
+__device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
+                           const int32_t (&v)[K], const int32_t (&rs)[K],
+                           const int32_t (&rd)[K], uint32_t complete,
+                           const int32_t* items, int n_items, Acc& acc) {
+  constexpr int J = K - 2;  // loop of the items
+  const Level L = plan.lv[K - 1];
+  const int lane = lane_id();
+  const bool use_src = L.src >= 0 && ((complete >> L.src) & 1u);
+  const int src_idx = use_src ? L.src - 2 : 0;
+  const uint32_t pos = use_src ? L.pos_src : L.isect;
+  const uint32_t neg = use_src ? L.neg_src : L.sub;
+  const bool item_bound = (L.bound == J);
+  const int32_t Bu = (L.bound >= 0 && !item_bound) ? v[L.bound] : INF;
+  const int32_t* srcset = M.set[src_idx];
+  const int src_full = use_src ? M.set_len[src_idx] : 0;
+
+  // bounded lengths of the rows of loops j < J (exact when the bound does
+  // not depend on the item; otherwise the full row, an upper bound that is
+  // still correct for membership probes)
+  int ulen[K];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    ulen[j] = 0;
+    if (((pos | neg) >> j) & 1u)
+      ulen[j] = item_bound ? rd[j] : bounded_len(g, v[j], rs[j], rd[j], Bu, L.bound == j);
+  }
+
+  for (int g0 = 0; g0 < n_items; g0 += WAVE) {
+    const int t = g0 + lane;
+    const bool valid = t < n_items;
+    const int32_t u = valid ? items[t] : 0;
+    const int32_t urs = valid ? g.rowptr[u] : 0;
+    const int32_t urd = valid ? g.rowptr[u + 1] - urs : 0;
+    const int32_t B = item_bound ? u : Bu;
+    int slot = SRC_SLOT, blen = INF, bstart = 0, slen = 0;
+    if (valid) {
+      if (use_src) {
+        slen = (L.src == J && item_bound) ? t : lower_bound(srcset, src_full, B);
+        blen = slen;
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if ((pos >> j) & 1u) {
+          int len = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
+          if (len < blen) {
+            blen = len;
+            slot = j;
+            bstart = rs[j];
+          }
+        }
+      }
+      if ((pos >> J) & 1u) {
+        int len = bounded_len(g, u, urs, urd, B, item_bound);
+        if (len < blen) {
+          blen = len;
+          slot = J;
+          bstart = urs;
+        }
+      }
+      if (INSTR) {
+        const uint32_t all = L.isect | L.sub;
+        unsigned long long b = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if ((all >> j) & 1u)
+            b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
+        if ((all >> J) & 1u) b += 4ull * (unsigned)bounded_len(g, u, urs, urd, B, item_bound) + 8ull;
+        acc.bytes += b;
+      }
+    } else {
+      blen = 0;
+    }
+    int total;
+    const int pref = wave_excl_scan(blen, &total);
+    M.it_u[lane] = u;
+    M.it_pref[lane] = pref;
+    M.it_bstart[lane] = bstart;
+    M.it_slot[lane] = slot;
+    M.it_srclen[lane] = slen;
+    M.it_urs[lane] = urs;
+    M.it_urd[lane] = urd;
+    wave_sync();
+    const int nvalid = min(WAVE, n_items - g0);
+    for (int p0 = 0; p0 < total; p0 += WAVE) {
+      const int p = p0 + lane;
+      bool ok = p < total;
+      if (ok) {
+        // item of pair p: the last i with pref[i] <= p
+        int lo = 0, hi = nvalid;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (M.it_pref[mid] <= p) lo = mid + 1; else hi = mid;
+        }
+        const int i = lo - 1;
+        const int e = p - M.it_pref[i];
+        const int sl = M.it_slot[i];
+        const int32_t x = (sl == SRC_SLOT) ? srcset[e] : g.col[M.it_bstart[i] + e];
+        const int32_t uu = M.it_u[i];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if ((L.excl >> j) & 1u) ok = ok && (x != v[j]);
+        if ((L.excl >> J) & 1u) ok = ok && (x != uu);
+        if (ok && use_src && sl != SRC_SLOT) ok = contains(srcset, M.it_srclen[i], x);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if (ok && ((pos >> j) & 1u) && sl != j) ok = contains(g.col + rs[j], ulen[j], x);
+        if (ok && ((pos >> J) & 1u) && sl != J)
+          ok = contains(g.col + M.it_urs[i], M.it_urd[i], x);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], ulen[j], x);
+        if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + M.it_urs[i], M.it_urd[i], x);
+      }
+      acc.cnt += ok ? 1ull : 0ull;
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------- materialised loops
+
+template <int K, int I, bool INSTR>
+__device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
+                          int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
+                          uint32_t complete, Acc& acc) {
+  const Level L = plan.lv[I];
+  const int lane = lane_id();
+  const int32_t B = L.bound >= 0 ? v[L.bound] : INF;
+  if (INSTR && lane == 0) {
+    const uint32_t all = L.isect | L.sub;
+    unsigned long long b = 0;
+#pragma unroll
+    for (int j = 0; j < I; ++j)
+      if ((all >> j) & 1u)
+        b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
+    acc.bytes += b;
+  }
+  const bool use_src = L.src >= 0 && ((complete >> L.src) & 1u);
+  const int src_idx = use_src ? L.src - 2 : 0;
+  const int32_t* srcset = M.set[src_idx];
+  const int src_len = use_src ? lower_bound(srcset, M.set_len[src_idx], B) : 0;
+  const uint32_t pos = use_src ? L.pos_src : L.isect;
+  const uint32_t neg = use_src ? L.neg_src : L.sub;
+
+  int blen = use_src ? src_len : INF, slot = SRC_SLOT, bstart = 0;
+  int len[K];
+#pragma unroll
+  for (int j = 0; j < I; ++j) {
+    len[j] = 0;
+    if (((pos | neg) >> j) & 1u) len[j] = bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j);
+    if (((pos >> j) & 1u) && len[j] < blen) {
+      blen = len[j];
+      slot = j;
+      bstart = rs[j];
+    }
+  }
+  blen = uni(blen);
+  slot = uni(slot);
+  bstart = uni(bstart);
+
+  int32_t* out = M.set[I - 2];
+  uint32_t mine = complete & ~(1u << I);
+  if (blen <= CH) mine |= 1u << I;
+  for (int c0 = 0; c0 < blen; c0 += CH) {
+    const int c1 = min(blen, c0 + CH);
+    int nout = 0;
+    for (int r = c0; r < c1; r += WAVE) {
+      const int idx = r + lane;
+      bool ok = idx < c1;
+      int32_t x = 0;
+      if (ok) x = (slot == SRC_SLOT) ? srcset[idx] : g.col[bstart + idx];
+#pragma unroll
+      for (int j = 0; j < I; ++j)
+        if ((L.excl >> j) & 1u) ok = ok && (x != v[j]);
+      if (ok && use_src && slot != SRC_SLOT) ok = contains(srcset, src_len, x);
+#pragma unroll
+      for (int j = 0; j < I; ++j)
+        if (ok && ((pos >> j) & 1u) && slot != j) ok = contains(g.col + rs[j], len[j], x);
+#pragma unroll
+      for (int j = 0; j < I; ++j)
+        if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], len[j], x);
+      const unsigned long long m = __ballot(ok);
+      if (ok) out[nout + mbcnt(m)] = x;
+      nout += __popcll(m);
+    }
+    if (lane == 0) M.set_len[I - 2] = nout;
+    wave_sync();
+    if constexpr (I == K - 2) {
+      last_level<K, INSTR>(g, plan, M, v, rs, rd, mine, out, nout, acc);
+    } else {
+      for (int t = 0; t < nout; ++t) {
+        v[I] = uni(out[t]);
+        rs[I] = uni(g.rowptr[v[I]]);
+        rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
+        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, acc);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// --------------------------------------------------------------- kernels
+
+__device__ __forceinline__ void add_u128(unsigned long long* lo_hi,
+                                         unsigned long long lo,
+                                         unsigned long long hi) {
+  unsigned long long old = atomicAdd(lo_hi, lo);
+  if (old + lo < old) hi += 1;
+  if (hi) atomicAdd(lo_hi + 1, hi);
+}
+
+// 128-bit sum over the wave of one 64-bit value per lane, on lane 0
+__device__ __forceinline__ void wave_sum_u128(unsigned long long x,
+                                              unsigned long long* lo,
+                                              unsigned long long* hi) {
+  unsigned long long a = x & 0xffffffffull, b = x >> 32;
+#pragma unroll
+  for (int d = WAVE / 2; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, WAVE);
+    b += __shfl_xor(b, d, WAVE);
+  }
+  // x_total = b * 2^32 + a, with a, b < 2^38
+  unsigned long long l = a + (b << 32);
+  unsigned long long h = (b >> 32) + (l < a ? 1ull : 0ull);
+  *lo = l;
+  *hi = h;
+}
+
+template <int K, bool PER_ROOT, bool INSTR>
+__global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out o) {
+  __shared__ WaveMem<K> mem[WPB];
+  WaveMem<K>& M = mem[threadIdx.x / WAVE];
+  const int lane = lane_id();
+  Acc acc{0ull, 0ull};
+  int32_t v[K], rs[K], rd[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = rs[j] = rd[j] = 0;
+
+  for (;;) {
+    long long t0 = 0;
+    if (lane == 0) t0 = (long long)atomicAdd(o.acc + 4, (unsigned long long)T.batch);
+    t0 = __shfl(t0, 0, WAVE);
+    if (t0 >= T.n_tasks) break;
+    const long long t1 = min(t0 + (long long)T.batch, T.n_tasks);
+    for (long long t = t0; t < t1; ++t) {
+      // root of task t: the last r with prefix[r] <= t
+      long long lo = 0, hi = T.n_roots + 1;
+      while (lo < hi) {
+        long long mid = (lo + hi) >> 1;
+        if (T.prefix[mid] <= t) lo = mid + 1; else hi = mid;
+      }
+      const long long r = lo - 1;
+      const int32_t v0 = uni(T.roots ? T.roots[r] : (int32_t)r);
+      const int32_t rs0 = uni(g.rowptr[v0]);
+      const int32_t rd0 = uni(g.rowptr[v0 + 1]) - rs0;
+      const int32_t len1 = T.bounded1 ? uni(g.lo[v0]) : rd0;
+      const int32_t begin = (int32_t)(t - T.prefix[r]) * T.chunk;
+      const int32_t end = min(begin + T.chunk, len1);
+      v[0] = v0;
+      rs[0] = rs0;
+      rd[0] = rd0;
+      if constexpr (K == 2) {
+        if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
+      } else if constexpr (K == 3) {
+        last_level<K, INSTR>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
+                             end - begin, acc);
+      } else {
+        for (int32_t i = begin; i < end; ++i) {
+          v[1] = uni(g.col[rs0 + i]);
+          rs[1] = uni(g.rowptr[v[1]]);
+          rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
+          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, acc);
+        }
+      }
+      if constexpr (PER_ROOT) {
+        unsigned long long l, h;
+        wave_sum_u128(acc.cnt, &l, &h);
+        if (lane == 0) {
+          unsigned long long old = atomicAdd(o.per_root + r, l);
+          if (h || old + l < old) atomicOr(o.acc + 5, 1ull);
+        }
+        acc.cnt = 0;
+      }
+    }
+  }
+  unsigned long long l, h;
+  wave_sum_u128(acc.cnt, &l, &h);
+  if (lane == 0 && (l | h)) add_u128(o.acc, l, h);
+  if (INSTR) {
+    wave_sum_u128(acc.bytes, &l, &h);
+    if (lane == 0 && (l | h)) add_u128(o.acc + 2, l, h);
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+}  // namespace dev
+
+// ------------------------------------------------------------ host side
+
+namespace {
+
+#define GZ_HIP(call)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess) {                                               \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));     \
+      return GZ_EDEVICE;                                                  \
+    }                                                                     \
+  } while (0)
+
+template <int K, bool PR, bool IN>
+gz_status launch_k(const dev::Graph& g, const Plan& plan, const dev::Tasks& T,
+                   const dev::Out& o, hipStream_t st) {
+  auto kern = dev::k_mine<K, PR, IN>;
+  int per_cu = 0;
+  GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, dev::BLOCK, 0));
+  int devid = 0;
+  GZ_HIP(hipGetDevice(&devid));
+  int cus = 0;
+  GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  long long blocks = (long long)std::max(per_cu, 1) * std::max(cus, 1);
+  long long need = (T.n_tasks + (long long)T.batch * dev::WPB - 1) /
+                   ((long long)T.batch * dev::WPB);
+  blocks = std::max(1ll, std::min(blocks, need));
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(dev::BLOCK), 0, st, g, plan, T, o);
+  GZ_HIP(hipGetLastError());
+  return GZ_OK;
+}
+
+template <bool PR, bool IN>
+gz_status launch_by_k(int k, const dev::Graph& g, const Plan& plan,
+                      const dev::Tasks& T, const dev::Out& o, hipStream_t st) {
+  switch (k) {
+    case 2: return launch_k<2, PR, IN>(g, plan, T, o, st);
+    case 3: return launch_k<3, PR, IN>(g, plan, T, o, st);
+    case 4: return launch_k<4, PR, IN>(g, plan, T, o, st);
+    case 5: return launch_k<5, PR, IN>(g, plan, T, o, st);
+    case 6: return launch_k<6, PR, IN>(g, plan, T, o, st);
+    case 7: return launch_k<7, PR, IN>(g, plan, T, o, st);
+    case 8: return launch_k<8, PR, IN>(g, plan, T, o, st);
+    default:
+      set_error("pattern size out of range");
+      return GZ_EINVAL;
+  }
+}
+
+int chunk_for(int k) { return k <= 2 ? (1 << 30) : (k == 3 ? 64 : 16); }
+
+}  // namespace
+
+// First-loop length of a root, for the task split.
+static inline int64_t len1_of(const HostGraph& h, int32_t v, bool bounded1) {
+  return bounded1 ? h.lo[v] : (h.rowptr[v + 1] - h.rowptr[v]);
+}
+
+static gz_status upload_prefix(const std::vector<int64_t>& pre, int64_t** out,
+                               hipStream_t st) {
+  int64_t* d = nullptr;
+  GZ_HIP(hipMalloc(&d, pre.size() * sizeof(int64_t)));
+  hipError_t e = hipMemcpyAsync(d, pre.data(), pre.size() * sizeof(int64_t),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    set_error(std::string("task prefix upload: ") + hipGetErrorString(e));
+    return GZ_EDEVICE;
+  }
+  *out = d;
+  return GZ_OK;
+}
+
+// Cached all-roots task prefix for (bounded1, chunk).
+static gz_status graph_tasks(const gz_graph* g, bool bounded1, int chunk,
+                             hipStream_t st, DevTasks* out) {
+  const int64_t key = (int64_t)chunk * 2 + (bounded1 ? 1 : 0);
+  std::lock_guard<std::mutex> lock(g->task_mu);
+  for (auto& kv : g->task_cache)
+    if (kv.first == key) {
+      *out = kv.second;
+      return GZ_OK;
+    }
+  const HostGraph& h = g->host;
+  std::vector<int64_t> pre((size_t)h.n + 1, 0);
+  for (int32_t v = 0; v < h.n; ++v)
+    pre[v + 1] = pre[v] + (len1_of(h, v, bounded1) + chunk - 1) / chunk;
+  DevTasks dt;
+  dt.n_tasks = pre[h.n];
+  gz_status rc = upload_prefix(pre, &dt.prefix, st);
+  if (rc) return rc;
+  g->task_cache.emplace_back(key, dt);
+  *out = dt;
+  return GZ_OK;
+}
+
+gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
+                    const int32_t* roots, int64_t n_roots, uint64_t* per_root,
+                    bool instr, unsigned __int128* total, unsigned __int128* bytes,
+                    float* kernel_ms) {
+  const Plan& plan = s->plan;
+  const HostGraph& h = g->host;
+  const bool bounded1 = plan.lv[1].bound == 0;
+  const int chunk = chunk_for(plan.k);
+  const bool pr = roots != nullptr;
+
+  DevTasks tasks;
+  int64_t* own_prefix = nullptr;
+  int32_t* d_roots = nullptr;
+  int64_t nr = h.n;
+  if (!pr) {
+    gz_status rc = graph_tasks(g, bounded1, chunk, st, &tasks);
+    if (rc) return rc;
+  } else {
+    nr = n_roots;
+    std::vector<int64_t> pre((size_t)nr + 1, 0);
+    for (int64_t i = 0; i < nr; ++i)
+      pre[i + 1] = pre[i] + (len1_of(h, roots[i], bounded1) + chunk - 1) / chunk;
+    tasks.n_tasks = pre[nr];
+    gz_status rc = upload_prefix(pre, &own_prefix, st);
+    if (rc) return rc;
+    tasks.prefix = own_prefix;
+    if (hipMalloc(&d_roots, sizeof(int32_t) * std::max<int64_t>(nr, 1)) != hipSuccess ||
+        hipMemcpyAsync(d_roots, roots, sizeof(int32_t) * nr, hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+      (void)hipFree(own_prefix);
+      (void)hipFree(d_roots);
+      set_error("root list upload failed");
+      return GZ_EDEVICE;
+    }
+  }
+
+  unsigned long long* d_acc = nullptr;
+  const long long n_acc = 8 + (pr ? nr : 0);
+  gz_status rc = GZ_OK;
+  if (hipMalloc(&d_acc, sizeof(unsigned long long) * n_acc) != hipSuccess) {
+    set_error("device allocation of the accumulators failed");
+    rc = GZ_ENOMEM;
+  }
+  if (!rc) {
+    hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
+                       dim3(256), 0, st, d_acc, n_acc);
+    dev::Graph dg{g->d_rowptr, g->d_col, g->d_lo, h.n};
+    dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1, 0};
+    dev::Out o{d_acc, d_acc + 8};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (kernel_ms) {
+      *kernel_ms = 0.0f;
+      if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
+          hipEventRecord(ev0, st) != hipSuccess) {
+        set_error("hipEvent set-up failed");
+        rc = GZ_EDEVICE;
+      }
+    }
+    if (!rc && tasks.n_tasks > 0) {
+      if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
+      else if (pr) rc = launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
+      else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
+      else rc = launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
+    }
+    if (kernel_ms && !rc) {
+      if (hipEventRecord(ev1, st) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess ||
+          hipEventElapsedTime(kernel_ms, ev0, ev1) != hipSuccess) {
+        set_error("hipEvent timing failed");
+        rc = GZ_EDEVICE;
+      }
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+  std::vector<unsigned long long> hacc((size_t)n_acc, 0ull);
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(hacc.data(), d_acc, sizeof(unsigned long long) * n_acc,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      set_error(std::string("mining kernel: ") + hipGetErrorString(e));
+      rc = GZ_EDEVICE;
+    }
+  }
+  (void)hipFree(d_acc);
+  if (own_prefix) (void)hipFree(own_prefix);
+  if (d_roots) (void)hipFree(d_roots);
+  if (rc) return rc;
+
+  *total = ((unsigned __int128)hacc[1] << 64) | hacc[0];
+  if (bytes) {
+    unsigned __int128 b = ((unsigned __int128)hacc[3] << 64) | hacc[2];
+    // loop 1 is evaluated once per root: one list, N(v0), below its bound
+    for (int64_t i = 0; i < nr; ++i) {
+      int32_t v0 = pr ? roots[i] : (int32_t)i;
+      b += (unsigned __int128)(4 * len1_of(h, v0, bounded1) + 8);
+    }
+    *bytes = b;
+  }
+  if (pr) {
+    if (hacc[5]) {
+      set_error("a per-root count does not fit in 64 bits");
+      return GZ_EOVERFLOW;
+    }
+    for (int64_t i = 0; i < nr; ++i) per_root[i] = hacc[8 + i];
+  }
+  return GZ_OK;
+}
+
+void free_graph_tasks(gz_graph* g) {
+  for (auto& kv : g->task_cache) (void)hipFree(kv.second.prefix);
+  g->task_cache.clear();
+}
+
+}  // namespace gz
