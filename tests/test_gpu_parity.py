@@ -84,12 +84,13 @@ MEDIUM = ["triangle", "k4", "k5", "c4", "diamond", "tailed_triangle", "house", "
 
 
 def _medium_graphs():
-    yield "rmat11", synth.rmat_edges(11, 16, seed=21)
-    yield "cl4000", synth.chung_lu_edges(4000, 2.1, 14.0, 22, cap=False)
-    yield "er600", synth.er_edges(600, 0.04, 23)
+    # hubs of the R-MAT graph exceed one materialised chunk (256 elements)
+    yield "rmat10", synth.rmat_edges(10, 8, seed=21)
+    yield "cl2000", synth.chung_lu_edges(2000, 2.3, 8.0, 22, cap=True)
+    yield "er400", synth.er_edges(400, 0.03, 23)
 
 
-@pytest.mark.parametrize("gname", ["rmat11", "cl4000", "er600"])
+@pytest.mark.parametrize("gname", ["rmat10", "cl2000", "er400"])
 def test_medium_graphs(gname):
     e = dict(_medium_graphs())[gname]
     G, O = _pair(e)
@@ -174,7 +175,9 @@ def test_edge_cases():
     # only self-loops and duplicates of one edge
     G = gz.load_edges(np.array([0, 1, 1, 2], np.int32), np.array([0, 2, 2, 1], np.int32), 3)
     assert gz.count(G, edge) == 1 and gz.count(G, tri) == 0
-    assert list(gz.count_roots(G, edge, np.array([0, 1, 2], np.int32))) == [0, 0, 1]
+    # reindexed: old 1 -> 0, old 2 -> 1, old 0 -> 2; the edge {0,1} is found
+    # from its larger-id end (the bound makes loop 1 smaller than loop 0)
+    assert list(gz.count_roots(G, edge, np.array([0, 1, 2], np.int32))) == [0, 1, 0]
     # one vertex
     G = gz.load_edges(np.zeros(0, np.int32), np.zeros(0, np.int32), 1)
     assert gz.count(G, tri) == 0
