@@ -118,6 +118,9 @@ typedef struct {
     u128 count;
     /* instrumentation: one bound per position (Theorem 2 form) */
     int bound[8];
+    int extends[8];       /* position i extends position i-1's candidate set */
+    int added[8][8];      /* lists position i adds to that set              */
+    int32_t rank[8];      /* rank of m[i] among position i's candidates     */
     u128 bytes;
     int instrument;
 } search_t;
@@ -141,15 +144,50 @@ static int64_t prefix_len(const search_t* s, int32_t u, int64_t b) {
 }
 
 /* Algorithmic bytes of evaluating position i's candidate set from the
- * current partial mapping m[0..i-1]: for every earlier position j whose list
- * enters the set expression (black neighbours, and red ones in induced mode)
- * 4 bytes per element of N(m[j]) below the position's bound plus 8 bytes for
- * the list's two row offsets. */
+ * current partial mapping m[0..i-1].  Written as a bounded linear merge, the
+ * set expression reads, for every earlier position j whose list enters it
+ * (black neighbours, and red ones in induced mode), the elements of N(m[j])
+ * below the position's bound: 4 bytes each, plus 8 bytes for the list's two
+ * row offsets.  When the position extends the candidate set of position i-1
+ * (see extension_rule) it reads instead that set's elements below m[i-1]
+ * (their number is m[i-1]'s rank in it) and only the lists it adds. */
 static void add_level_bytes(search_t* s, int i) {
     int64_t b = (s->bound[i] >= 0) ? (int64_t)s->m[s->bound[i]] : INT64_MAX;
+    if (s->extends[i]) {
+        s->bytes += (u128)(4 * (int64_t)s->rank[i - 1]);
+        for (int j = 0; j < i; ++j)
+            if (s->added[i][j]) s->bytes += (u128)(4 * prefix_len(s, s->m[j], b) + 8);
+        return;
+    }
     for (int j = 0; j < i; ++j) {
         if (s->black[i][j] || s->induced) {
             s->bytes += (u128)(4 * prefix_len(s, s->m[j], b) + 8);
+        }
+    }
+}
+
+/* Position i (3 <= i <= k-1) extends position i-1's candidate set when it is
+ * bounded by position i-1 and every list of position i-1's set expression is
+ * also a list of position i's, with the same role (intersected or, in
+ * induced mode, subtracted).  Its added lists are the remaining ones. */
+static void extension_rule(search_t* s) {
+    for (int i = 0; i < s->k; ++i) {
+        s->extends[i] = 0;
+        for (int j = 0; j < 8; ++j) s->added[i][j] = 0;
+    }
+    for (int i = 3; i < s->k; ++i) {
+        if (s->bound[i] != i - 1) continue;
+        int ok = 1;
+        for (int j = 0; j < i - 1; ++j) {
+            if (s->black[i - 1][j] && !s->black[i][j]) ok = 0;
+            if (s->induced && !s->black[i - 1][j] && s->black[i][j]) ok = 0;
+        }
+        if (!ok) continue;
+        s->extends[i] = 1;
+        for (int j = 0; j < i; ++j) {
+            int in_i = s->black[i][j] || s->induced;
+            int in_prev = (j < i - 1) && (s->black[i - 1][j] || s->induced);
+            s->added[i][j] = in_i && !in_prev;
         }
     }
 }
@@ -169,6 +207,7 @@ static void dfs(search_t* s, int i) {
     for (int a = 0; a < i; ++a)
         if (s->upper[i][a] && s->m[a] < ub) ub = s->m[a];
     int32_t u = s->m[src];
+    int32_t accepted = 0;
     for (int64_t e = s->rowptr[u]; e < s->rowptr[u + 1]; ++e) {
         int32_t x = s->col[e];
         if (x >= ub) break;
@@ -184,8 +223,10 @@ static void dfs(search_t* s, int i) {
             s->count += 1;
         } else {
             s->m[i] = x;
+            s->rank[i] = accepted;
             dfs(s, i + 1);
         }
+        ++accepted;
     }
 }
 
@@ -257,6 +298,7 @@ int oracle_instrument(int32_t n, const int64_t* rowptr, const int32_t* col,
     int rc = setup(&s, n, rowptr, col, k, adj, induced, order, nr, ra, rb);
     if (rc) return rc;
     for (int i = 0; i < k; ++i) s.bound[i] = bound[i];
+    extension_rule(&s);
     s.instrument = 1;
     int64_t cnt = roots ? n_roots : (int64_t)n;
     u128 total = 0;

@@ -178,6 +178,13 @@ Plan lower_plan(const Pattern& p, const int8_t* order, const int8_t* bound,
       if (!adjacent && !implied) L.excl |= (uint8_t)(1u << j);
     }
   }
+  // byte accounting: extension of the enclosing loop's set
+  for (int i = 3; i < p.k; ++i) {
+    Level& L = plan.lv[i];
+    const Level& E = plan.lv[i - 1];
+    if (L.bound == i - 1 && !(E.isect & ~L.isect) && !(E.sub & ~L.sub))
+      L.acct = (uint8_t)(0x80u | ((L.isect | L.sub) & ~(E.isect | E.sub)));
+  }
   // reusable materialised sets: loops 2..k-2 are materialised
   for (int i = 3; i < p.k; ++i) {
     Level& L = plan.lv[i];

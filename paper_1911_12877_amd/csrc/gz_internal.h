@@ -33,6 +33,12 @@ constexpr int kMaxK = 8;
 //           bound is no tighter; loop i may filter that set instead of
 //           intersecting lists; -1 when there is none
 //   pos_src / neg_src : isect / sub bits still to check when filtering src
+//   acct  : accounting of algorithmic bytes (the instrumented pass only).
+//           Bit 7 set when loop i extends the enclosing loop's set: loop
+//           i-1 >= 2 is materialised, loop i is bounded by it, and loop
+//           i-1's intersected and subtracted lists are subsets of loop i's.
+//           Bits 0..6 then name the lists loop i adds; the enclosing set
+//           contributes its elements below v_{i-1}.
 struct Level {
   uint8_t isect;
   uint8_t sub;
@@ -41,7 +47,7 @@ struct Level {
   int8_t src;
   uint8_t pos_src;
   uint8_t neg_src;
-  uint8_t pad;
+  uint8_t acct;
 };
 
 struct Plan {
@@ -109,6 +115,19 @@ struct DevTasks {
   int64_t n_tasks = 0;
 };
 
+// Root lists of the clique path: light roots (3 <= lo <= 64) for the wave
+// kernel, heavy roots (lo > 64) for the workgroup kernel, the latter in order
+// of decreasing lo so that the largest start first.  Device arrays.
+struct CliqueLists {
+  int32_t* light_v = nullptr;
+  int32_t* light_r = nullptr;
+  int64_t n_light = 0;
+  int32_t* heavy_v = nullptr;
+  int32_t* heavy_r = nullptr;
+  int64_t n_heavy = 0;
+  int32_t heavy_max_lo = 0;
+};
+
 void set_error(const std::string& msg);
 
 }  // namespace gz
@@ -125,6 +144,9 @@ struct gz_graph {
   // first use and kept for the handle's life
   mutable std::mutex task_mu;
   mutable std::vector<std::pair<int64_t, gz::DevTasks>> task_cache;
+  // clique-path root lists over all roots, built on first use
+  mutable bool clique_ready = false;
+  mutable gz::CliqueLists clique_all;
 };
 
 struct gz_schedule {

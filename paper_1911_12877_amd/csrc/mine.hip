@@ -144,7 +144,7 @@ template <int K, bool INSTR>
 __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                            const int32_t (&v)[K], const int32_t (&rs)[K],
                            const int32_t (&rd)[K], uint32_t complete,
-                           const int32_t* items, int n_items, Acc& acc) {
+                           const int32_t* items, int n_items, int item_base, Acc& acc) {
   constexpr int J = K - 2;  // loop of the items
   const Level L = plan.lv[K - 1];
   const int lane = lane_id();
@@ -201,8 +201,11 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         }
       }
       if (INSTR) {
-        const uint32_t all = L.isect | L.sub;
-        unsigned long long b = 0;
+        // extension of the enclosing set: its elements below u (the item's
+        // rank) plus the added lists; otherwise every list of the loop
+        const bool ext = (L.acct & 0x80u) != 0;
+        const uint32_t all = ext ? (L.acct & 0x7fu) : (uint32_t)(L.isect | L.sub);
+        unsigned long long b = ext ? 4ull * (unsigned)(item_base + t) : 0ull;
 #pragma unroll
         for (int j = 0; j < J; ++j)
           if ((all >> j) & 1u)
@@ -265,13 +268,15 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 template <int K, int I, bool INSTR>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
-                          uint32_t complete, Acc& acc) {
+                          uint32_t complete, int rank_prev, Acc& acc) {
   const Level L = plan.lv[I];
   const int lane = lane_id();
   const int32_t B = L.bound >= 0 ? v[L.bound] : INF;
   if (INSTR && lane == 0) {
-    const uint32_t all = L.isect | L.sub;
-    unsigned long long b = 0;
+    // rank_prev: position of v[I-1] in the enclosing loop's set
+    const bool ext = (L.acct & 0x80u) != 0;
+    const uint32_t all = ext ? (L.acct & 0x7fu) : (uint32_t)(L.isect | L.sub);
+    unsigned long long b = ext ? 4ull * (unsigned)rank_prev : 0ull;
 #pragma unroll
     for (int j = 0; j < I; ++j)
       if ((all >> j) & 1u)
@@ -304,6 +309,7 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
   int32_t* out = M.set[I - 2];
   uint32_t mine = complete & ~(1u << I);
   if (blen <= CH) mine |= 1u << I;
+  int cum = 0;  // survivors of earlier chunks: rank of this chunk's first element
   for (int c0 = 0; c0 < blen; c0 += CH) {
     const int c1 = min(blen, c0 + CH);
     int nout = 0;
@@ -329,15 +335,16 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     if (lane == 0) M.set_len[I - 2] = nout;
     wave_sync();
     if constexpr (I == K - 2) {
-      last_level<K, INSTR>(g, plan, M, v, rs, rd, mine, out, nout, acc);
+      last_level<K, INSTR>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
     } else {
       for (int t = 0; t < nout; ++t) {
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, acc);
+        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, cum + t, acc);
       }
     }
+    cum += nout;
     wave_sync();
   }
 }
@@ -406,13 +413,13 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
         if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
       } else if constexpr (K == 3) {
         last_level<K, INSTR>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
-                             end - begin, acc);
+                             end - begin, begin, acc);
       } else {
         for (int32_t i = begin; i < end; ++i) {
           v[1] = uni(g.col[rs0 + i]);
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
-          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, acc);
+          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, i, acc);
         }
       }
       if constexpr (PER_ROOT) {
@@ -432,6 +439,262 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
   if (INSTR) {
     wave_sum_u128(acc.bytes, &l, &h);
     if (lane == 0 && (l | h)) add_u128(o.acc + 2, l, h);
+  }
+}
+
+// ------------------------------------------------------ clique fast path
+//
+// K_k (k >= 4) with its chain of bounds (every loop below the previous one):
+// the loops after v0 only ever intersect the candidates with lists of
+// vertices that are themselves candidates, all inside C1 = N(v0) ∩ [0, v0)
+// (the first lo[v0] entries of v0's row).  So C1 is staged in LDS once per
+// root and its adjacency stored as bit rows: bit q of row p says that C1[q]
+// (smaller than C1[p]) is a neighbour of C1[p], i.e. row p is the bounded
+// intersection C1 ∩ N(C1[p]) ∩ [0, C1[p]) of the loop after C1[p].  Every
+// deeper bounded intersection is then an AND of rows and the last loop a
+// popcount.  Roots with at most 64 candidates run one wave per root with a
+// single word per row; larger ones run one workgroup per root with multi-word
+// rows in dynamic LDS.
+
+struct RootList {
+  const int32_t* __restrict__ v;  // root vertices
+  const int32_t* __restrict__ r;  // output slot of each root (per-root mode)
+  long long n;
+};
+
+constexpr int CW = 64;
+constexpr int CBLOCK = 512;            // workgroup path: 8 waves per root
+constexpr int CWPB = CBLOCK / WAVE;
+
+struct CliqueWaveMem {
+  int32_t xs[CW];
+  unsigned long long rows[CW];
+  int32_t pref[CW];
+  int32_t slot[CW];
+  int32_t urs[CW];
+  int32_t ulen[CW];
+};
+
+// Cliques with D+1 more vertices inside AND(rows[ids[0..n)]) restricted to
+// words [0, nw): for D == 0 the popcount, otherwise a sum over the set's
+// members b, descending into rows[b] (whose bits all lie below b).
+template <int D>
+__device__ unsigned long long cl_count(const unsigned long long* rows, int W, int (&ids)[8],
+                                       int n, int nw) {
+  unsigned long long total = 0;
+  for (int w = 0; w < nw; ++w) {
+    unsigned long long s = ~0ull;
+    for (int t = 0; t < n; ++t) s &= rows[ids[t] * W + w];
+    if constexpr (D == 0) {
+      total += (unsigned long long)__popcll(s);
+    } else {
+      while (s) {
+        const int b = w * 64 + __builtin_ctzll(s);
+        s &= s - 1;
+        ids[n] = b;
+        total += cl_count<D - 1>(rows, W, ids, n + 1, w + 1);
+      }
+    }
+  }
+  return total;
+}
+
+// K-cliques of the root that take C1[a] as their second vertex and a member
+// of word w of row a as their third
+template <int K>
+__device__ __forceinline__ unsigned long long clique_unit(const unsigned long long* rows, int W,
+                                                         int a, int w) {
+  int ids[8];
+  ids[0] = a;
+  unsigned long long s = rows[a * W + w];
+  unsigned long long total = 0;
+  while (s) {
+    const int b = w * 64 + __builtin_ctzll(s);
+    s &= s - 1;
+    ids[1] = b;
+    total += cl_count<K - 4>(rows, W, ids, 2, w + 1);
+  }
+  return total;
+}
+
+// Probe plan of row p: slot 0 probes C1[0..p) into N+(C1[p]) (binary search
+// in global memory); slot 1 scans N+(C1[p]) and probes each element into
+// C1[0..p) (binary search in LDS) - cheaper unless N+(C1[p]) is much longer.
+__device__ __forceinline__ void row_plan(const Graph& g, int32_t x, int p, int32_t* urs,
+                                         int32_t* ulen, int32_t* slot, int* len) {
+  const int32_t lx = g.lo[x];
+  *urs = g.rowptr[x];
+  *ulen = lx;
+  const bool scan = lx <= 4 * p;
+  *slot = scan ? 1 : 0;
+  *len = scan ? lx : p;
+}
+
+__device__ __forceinline__ int row_probe(const Graph& g, const int32_t* xs, int a, int e,
+                                         int32_t slot, int32_t urs, int32_t ulen) {
+  if (slot == 0) return contains(g.col + urs, ulen, xs[e]) ? e : -1;
+  const int32_t y = g.col[urs + e];
+  const int q = lower_bound(xs, a, y);
+  return (q < a && xs[q] == y) ? q : -1;
+}
+
+// Wave path: roots with at most 64 candidates.
+template <int K, bool PER_ROOT>
+__global__ __launch_bounds__(BLOCK) void k_clique_wave(Graph g, RootList L, Out o, int batch) {
+  __shared__ CliqueWaveMem mem[WPB];
+  CliqueWaveMem& M = mem[threadIdx.x / WAVE];
+  const int lane = lane_id();
+  unsigned long long cnt = 0;
+  for (;;) {
+    long long t0 = 0;
+    if (lane == 0) t0 = (long long)atomicAdd(o.acc + 4, (unsigned long long)batch);
+    t0 = __shfl(t0, 0, WAVE);
+    if (t0 >= L.n) break;
+    const long long t1 = min(t0 + (long long)batch, L.n);
+    for (long long t = t0; t < t1; ++t) {
+      const int32_t v0 = uni(L.v[t]);
+      const int d = uni(g.lo[v0]);
+      if (d >= K - 1) {
+        const int32_t rs0 = uni(g.rowptr[v0]);
+        int len = 0;
+        if (lane < d) {
+          M.xs[lane] = g.col[rs0 + lane];
+          row_plan(g, M.xs[lane], lane, &M.urs[lane], &M.ulen[lane], &M.slot[lane], &len);
+        }
+        M.rows[lane] = 0ull;
+        int total;
+        M.pref[lane] = wave_excl_scan(len, &total);
+        wave_sync();
+        for (int p0 = 0; p0 < total; p0 += WAVE) {
+          const int p = p0 + lane;
+          if (p < total) {
+            int lo2 = 0, hi2 = d;
+            while (lo2 < hi2) {
+              int mid = (lo2 + hi2) >> 1;
+              if (M.pref[mid] <= p) lo2 = mid + 1; else hi2 = mid;
+            }
+            const int a = lo2 - 1;
+            const int bit = row_probe(g, M.xs, a, p - M.pref[a], M.slot[a], M.urs[a], M.ulen[a]);
+            if (bit >= 0) atomicOr(&M.rows[a], 1ull << bit);
+          }
+        }
+        wave_sync();
+        if (lane < d) cnt += clique_unit<K>(M.rows, 1, lane, 0);
+        wave_sync();
+      }
+      if constexpr (PER_ROOT) {
+        unsigned long long l, h;
+        wave_sum_u128(cnt, &l, &h);
+        if (lane == 0) {
+          unsigned long long old = atomicAdd(o.per_root + L.r[t], l);
+          if (h || old + l < old) atomicOr(o.acc + 5, 1ull);
+        }
+        cnt = 0;
+      }
+    }
+  }
+  if constexpr (!PER_ROOT) {
+    unsigned long long l, h;
+    wave_sum_u128(cnt, &l, &h);
+    if (lane == 0 && (l | h)) add_u128(o.acc, l, h);
+  }
+}
+
+// Workgroup path: roots with more than 64 candidates (at most 64 W).
+// Dynamic LDS: rows[S*W] (64-bit) then xs, pref, urs, ulen, slot (S int32
+// each), S = 64 W.
+template <int K, bool PER_ROOT>
+__global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Out o, int W) {
+  extern __shared__ unsigned long long dyn[];
+  __shared__ int s_task;
+  __shared__ int s_tot[CWPB];
+  const int S = 64 * W;
+  unsigned long long* rows = dyn;
+  int32_t* xs = (int32_t*)(rows + (size_t)S * W);
+  int32_t* pref = xs + S;
+  int32_t* urs = pref + S;
+  int32_t* ulen = urs + S;
+  int32_t* slot = ulen + S;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / WAVE;
+  unsigned long long cnt = 0;
+  for (;;) {
+    if (tid == 0) s_task = (int)atomicAdd(o.acc + 7, 1ull);
+    __syncthreads();
+    const long long t = s_task;
+    __syncthreads();
+    if (t >= L.n) break;
+    const int32_t v0 = L.v[t];
+    const int d = g.lo[v0];
+    const int32_t rs0 = g.rowptr[v0];
+    const int Wd = (d + 63) / 64;
+    for (int q = tid; q < d * Wd; q += CBLOCK) rows[(q / Wd) * W + (q % Wd)] = 0ull;
+    // probe lengths of the rows and their exclusive prefix over the block
+    const int per = (d + CBLOCK - 1) / CBLOCK;
+    int mysum = 0;
+    for (int j = 0; j < per; ++j) {
+      const int a = tid * per + j;
+      if (a < d) {
+        const int32_t x = g.col[rs0 + a];
+        xs[a] = x;
+        int len;
+        row_plan(g, x, a, &urs[a], &ulen[a], &slot[a], &len);
+        pref[a] = len;
+        mysum += len;
+      }
+    }
+    int wtot;
+    const int wexcl = wave_excl_scan(mysum, &wtot);
+    if (lane == 0) s_tot[wv] = wtot;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w2 = 0; w2 < CWPB; ++w2) {
+      if (w2 < wv) base += s_tot[w2];
+      total += s_tot[w2];
+    }
+    int run = base + wexcl;
+    for (int j = 0; j < per; ++j) {
+      const int a = tid * per + j;
+      if (a < d) {
+        const int l = pref[a];
+        pref[a] = run;
+        run += l;
+      }
+    }
+    __syncthreads();
+    for (int p = tid; p < total; p += CBLOCK) {
+      int lo2 = 0, hi2 = d;
+      while (lo2 < hi2) {
+        int mid = (lo2 + hi2) >> 1;
+        if (pref[mid] <= p) lo2 = mid + 1; else hi2 = mid;
+      }
+      const int a = lo2 - 1;
+      const int bit = row_probe(g, xs, a, p - pref[a], slot[a], urs[a], ulen[a]);
+      if (bit >= 0) atomicOr(&rows[a * W + (bit >> 6)], 1ull << (bit & 63));
+    }
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int q = tid; q < d * Wd; q += CBLOCK) {
+      const int a = q / Wd, w = q - a * Wd;
+      if (w * 64 < a) mine += clique_unit<K>(rows, W, a, w);
+    }
+    if constexpr (PER_ROOT) {
+      unsigned long long l, h;
+      wave_sum_u128(mine, &l, &h);
+      if (lane == 0 && (l | h)) {
+        unsigned long long old = atomicAdd(o.per_root + L.r[t], l);
+        if (h || old + l < old) atomicOr(o.acc + 5, 1ull);
+      }
+    } else {
+      cnt += mine;
+    }
+    __syncthreads();
+  }
+  if constexpr (!PER_ROOT) {
+    unsigned long long l, h;
+    wave_sum_u128(cnt, &l, &h);
+    if (lane == 0 && (l | h)) add_u128(o.acc, l, h);
   }
 }
 
@@ -492,6 +755,119 @@ gz_status launch_by_k(int k, const dev::Graph& g, const Plan& plan,
 }
 
 int chunk_for(int k) { return k <= 2 ? (1 << 30) : (k == 3 ? 64 : 16); }
+
+// K_k with every loop bounded by the previous one
+bool is_clique_chain(const Plan& p) {
+  for (int i = 1; i < p.k; ++i)
+    if (p.lv[i].isect != (uint8_t)((1u << i) - 1) || p.lv[i].sub != 0 || p.lv[i].bound != i - 1)
+      return false;
+  return true;
+}
+
+gz_status upload_i32(const std::vector<int32_t>& v, int32_t** out, hipStream_t st) {
+  *out = nullptr;
+  if (v.empty()) return GZ_OK;
+  GZ_HIP(hipMalloc(out, v.size() * sizeof(int32_t)));
+  GZ_HIP(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  return GZ_OK;
+}
+
+gz_status build_clique_lists(const HostGraph& h, const int32_t* roots, int64_t n_roots,
+                             hipStream_t st, CliqueLists* out) {
+  std::vector<int32_t> lv, lr;
+  std::vector<std::pair<int32_t, int32_t>> hv;  // (lo, index)
+  const int64_t nr = roots ? n_roots : h.n;
+  for (int64_t i = 0; i < nr; ++i) {
+    const int32_t v = roots ? roots[i] : (int32_t)i;
+    const int32_t d = h.lo[v];
+    if (d < 3) continue;
+    if (d <= dev::CW) {
+      lv.push_back(v);
+      lr.push_back((int32_t)i);
+    } else {
+      hv.emplace_back(d, (int32_t)i);
+    }
+  }
+  std::stable_sort(hv.begin(), hv.end(),
+                   [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                     return a.first > b.first;
+                   });
+  std::vector<int32_t> hvv, hvr;
+  for (auto& x : hv) {
+    hvv.push_back(roots ? roots[x.second] : x.second);
+    hvr.push_back(x.second);
+    out->heavy_max_lo = std::max(out->heavy_max_lo, x.first);
+  }
+  gz_status rc = upload_i32(lv, &out->light_v, st);
+  if (!rc) rc = upload_i32(lr, &out->light_r, st);
+  if (!rc) rc = upload_i32(hvv, &out->heavy_v, st);
+  if (!rc) rc = upload_i32(hvr, &out->heavy_r, st);
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("clique root list upload failed");
+    rc = GZ_EDEVICE;
+  }
+  out->n_light = (int64_t)lv.size();
+  out->n_heavy = (int64_t)hvv.size();
+  return rc;
+}
+
+void free_clique_lists(CliqueLists* c) {
+  for (int32_t* p : {c->light_v, c->light_r, c->heavy_v, c->heavy_r})
+    if (p) (void)hipFree(p);
+  *c = CliqueLists();
+}
+
+template <int K, bool PR>
+gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::Out& o,
+                          hipStream_t st) {
+  int devid = 0, cus = 0, per_cu = 0;
+  GZ_HIP(hipGetDevice(&devid));
+  GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  if (C.n_light > 0) {
+    const int batch = 8;
+    auto kw = dev::k_clique_wave<K, PR>;
+    GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kw, dev::BLOCK, 0));
+    long long blocks = (long long)std::max(per_cu, 1) * std::max(cus, 1);
+    long long need = (C.n_light + (long long)batch * dev::WPB - 1) / ((long long)batch * dev::WPB);
+    blocks = std::max(1ll, std::min(blocks, need));
+    dev::RootList L{C.light_v, C.light_r, C.n_light};
+    hipLaunchKernelGGL(kw, dim3((unsigned)blocks), dim3(dev::BLOCK), 0, st, g, L, o, batch);
+    GZ_HIP(hipGetLastError());
+  }
+  if (C.n_heavy > 0) {
+    auto kb = dev::k_clique_block<K, PR>;
+    const int W = (C.heavy_max_lo + 63) / 64;
+    const size_t S = 64 * (size_t)W;
+    const size_t lds = S * W * sizeof(unsigned long long) + 5 * S * sizeof(int32_t);
+    GZ_HIP(hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb, dev::CBLOCK, lds));
+    if (per_cu < 1) {
+      set_error("clique workgroup path does not fit in LDS");
+      return GZ_EDEVICE;
+    }
+    long long blocks = std::min<long long>((long long)per_cu * std::max(cus, 1), C.n_heavy);
+    dev::RootList L{C.heavy_v, C.heavy_r, C.n_heavy};
+    hipLaunchKernelGGL(kb, dim3((unsigned)blocks), dim3(dev::CBLOCK), lds, st, g, L, o, W);
+    GZ_HIP(hipGetLastError());
+  }
+  return GZ_OK;
+}
+
+template <bool PR>
+gz_status launch_clique(int k, const dev::Graph& g, const CliqueLists& C, const dev::Out& o,
+                        hipStream_t st) {
+  switch (k) {
+    case 4: return launch_clique_k<4, PR>(g, C, o, st);
+    case 5: return launch_clique_k<5, PR>(g, C, o, st);
+    case 6: return launch_clique_k<6, PR>(g, C, o, st);
+    case 7: return launch_clique_k<7, PR>(g, C, o, st);
+    case 8: return launch_clique_k<8, PR>(g, C, o, st);
+    default:
+      set_error("clique path needs 4 <= k <= 8");
+      return GZ_EINVAL;
+  }
+}
 
 }  // namespace
 
@@ -582,6 +958,24 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     set_error("device allocation of the accumulators failed");
     rc = GZ_ENOMEM;
   }
+  // clique fast path: K_k (k >= 4) with chain bounds, rows of at most 16 words
+  const bool use_clique = !instr && plan.k >= 4 && is_clique_chain(plan) && g->max_lo <= 1024;
+  CliqueLists own_lists;
+  const CliqueLists* lists = nullptr;
+  if (!rc && use_clique) {
+    if (!pr) {
+      std::lock_guard<std::mutex> lock(g->task_mu);
+      if (!g->clique_ready) {
+        rc = build_clique_lists(h, nullptr, 0, st, &g->clique_all);
+        if (rc) free_clique_lists(&g->clique_all);
+        else g->clique_ready = true;
+      }
+      lists = &g->clique_all;
+    } else {
+      rc = build_clique_lists(h, roots, nr, st, &own_lists);
+      lists = &own_lists;
+    }
+  }
   if (!rc) {
     hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
                        dim3(256), 0, st, d_acc, n_acc);
@@ -598,7 +992,10 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
       }
     }
     if (!rc && tasks.n_tasks > 0) {
-      if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
+      if (use_clique) {
+        rc = pr ? launch_clique<true>(plan.k, dg, *lists, o, st)
+                : launch_clique<false>(plan.k, dg, *lists, o, st);
+      } else if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
       else if (pr) rc = launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
       else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
       else rc = launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
@@ -624,6 +1021,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
   }
   (void)hipFree(d_acc);
+  free_clique_lists(&own_lists);
   if (own_prefix) (void)hipFree(own_prefix);
   if (d_roots) (void)hipFree(d_roots);
   if (rc) return rc;
@@ -651,6 +1049,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
 void free_graph_tasks(gz_graph* g) {
   for (auto& kv : g->task_cache) (void)hipFree(kv.second.prefix);
   g->task_cache.clear();
+  free_clique_lists(&g->clique_all);
+  g->clique_ready = false;
 }
 
 }  // namespace gz

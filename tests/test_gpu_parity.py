@@ -239,3 +239,34 @@ def test_strict_csr_rejects_malformed():
     assert ex.value.status == gz.GZ_EINVAL
     G = gz.load_graph(r, c, flags=gz.GRAPH_NORMALIZE)
     assert gz.graph_info(G)["nnz"] == 2
+
+
+def test_clique_paths_closed_forms():
+    """K_n: every C2 has n-2 elements, so n = 120 sends every edge with
+    C2 > 64 elements through the workgroup path with two-word rows."""
+    for n in (40, 120):
+        G = gz.load_edges(*synth.complete_edges(n))
+        for k in (5, 6, 7, 8):
+            _say("clique closed form", n, k)
+            assert gz.count(G, gz.compile_pattern(P.named(f"k{k}"), True)) == math.comb(n, k)
+
+
+@pytest.mark.parametrize("which", ["er_dense", "rmat10", "cl_core"])
+def test_clique_paths_vs_oracle(which):
+    if which == "er_dense":
+        e = synth.er_edges(200, 0.5, 111)
+    elif which == "rmat10":
+        e = synth.rmat_edges(10, 16, seed=112)
+    else:
+        e = synth.chung_lu_edges(3000, 2.1, 24.0, 113, cap=False)
+    G, O = _pair(e)
+    _say("clique vs oracle", which, gz.graph_info(G))
+    for k in (5, 6, 7):
+        pat = P.named(f"k{k}")
+        s = gz.compile_pattern(pat, True)
+        want = oracle.count(O, pat, True)
+        assert gz.count(G, s) == want, (which, k)
+        roots = np.arange(O.n, dtype=np.int32)
+        _, per = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                              roots=roots, per_root=True)
+        assert np.array_equal(gz.count_roots(G, s, roots), per), (which, k)

@@ -265,6 +265,29 @@ def test_per_root_decomposition():
     assert t2 == total == int(per.sum())
 
 
+def test_instrument_clique_extension_closed_form():
+    """K4, identity schedule, bounds v1<v0, v2<v1, v3<v2: loops 1 and 2 read
+    their lists below the bound; loop 3 extends loop 2's set C2 = N(v0) ∩
+    N(v1) ∩ [0, v1), reading the elements of C2 below v2 (v2's rank in C2)
+    and the part of N(v2) below v2."""
+    e = synth.chung_lu_edges(300, 2.3, 12.0, 72, cap=True)
+    g = oracle.from_edge_tuple(e)
+    lo = oracle.lo_end(g)
+    nb = [set(g.col[g.rowptr[v]:g.rowptr[v + 1]].tolist()) for v in range(g.n)]
+    want = int(np.sum(4 * lo + 8))
+    for v0 in range(g.n):
+        row0 = g.col[g.rowptr[v0]:g.rowptr[v0 + 1]]
+        for v1 in row0[row0 < v0]:
+            want += 4 * int(np.sum(row0 < v1)) + 4 * int(lo[v1]) + 16
+            c2 = sorted(x for x in nb[v0] & nb[v1] if x < v1)
+            for rank, v2 in enumerate(c2):
+                want += 4 * rank + 4 * int(lo[v2]) + 8
+    k4 = P.named("k4")
+    b, c = oracle.instrument(g, k4, True, (0, 1, 2, 3), [-1, 0, 1, 2])
+    assert b == want
+    assert c == oracle.count(g, k4)
+
+
 def test_instrument_triangle_closed_form():
     """Triangle, schedule (0,1,2), bounds v1<v0, v2<v1: level 1 reads the
     lower part of N(v0) once per root; level 2 reads N(v0) and N(v1) below
