@@ -208,6 +208,69 @@ gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_bytes,
                          uint64_t* out_count);
 
+/* ------------------------------------------------- learned schedule choice */
+
+/*
+ * The analytic model of Section 5.4 assumes a uniform random graph.  A
+ * learned cost model can rank the distinct schedules instead: a two-layer
+ * perceptron h = relu(W1 x + b1), y = w2 . h + b2 (H hidden units) maps the
+ * GZ_FEATURES features of a (schedule, graph) pair to a relative log10 run
+ * time.  Parameters are FP32 in one array
+ * [W1 (H x D, row-major), b1 (H), w2 (H), b2], GZ_MLP_PARAMS(D, H) floats.
+ */
+#define GZ_FEATURES 108
+#define GZ_MLP_PARAMS(D, H) ((int64_t)(H) * (D) + 2 * (int64_t)(H) + 1)
+#define GZ_SCHED_LEARNED 1u   /* gz_compile_pattern_graph: rank by the
+                                 installed model (analytic if none)       */
+
+/* Features of the schedule order[k] of a pattern on a prepared graph, into
+ * out[GZ_FEATURES] (host).  Per loop 1..7 (zero beyond k): presence, pattern
+ * neighbours/7, subtracted non-neighbours/7, bounded, bounded by the
+ * previous loop, unbounded with no reusable set, log10 of the loop size in
+ * G(n, p) with the graph's n and mean degree (/10), log10 restriction pass
+ * rate (/3), last loop, reusable set present, log10 of the loop's
+ * cost-model term (/10), intersected and subtracted lists whose owner is
+ * itself bounded (/7 each), length of the loop's bound chain (/7) - 14 per
+ * loop; then log10 of the whole schedule's cost in this graph's G(n, p) and
+ * in the paper's G(1000, 5/999) (/10 each); then graph statistics (log10 of
+ * n, edges, mean degree, E[d^2]/E[d], max degree, mean and E[lo^2]/E[lo]
+ * and max of the smaller-id degree lo, each scaled).  GZ_EINVAL for a bad
+ * pattern/order. */
+gz_status gz_schedule_features(const gz_graph* g, const uint8_t* adj, int32_t k,
+                               int32_t induced, const int8_t* order,
+                               float* out);
+
+/* Install (copy) a model for GZ_SCHED_LEARNED, process-wide; params NULL
+ * removes it.  D must be GZ_FEATURES, 1 <= H <= 1024. */
+gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H);
+
+/* gz_compile_pattern with the graph the schedule will run on.  With
+ * GZ_SCHED_LEARNED and an installed model the distinct schedule of lowest
+ * predicted cost is chosen (BF16 inference on the current device; ties
+ * within 1e-6 go to the explorer's first); otherwise as gz_compile_pattern.
+ * The count never depends on the choice (Theorem 1). */
+gz_status gz_compile_pattern_graph(const gz_graph* g, const uint8_t* adj,
+                                   int32_t k, int32_t induced, uint32_t flags,
+                                   gz_schedule** out);
+
+/*
+ * MLP kernels on device arrays (hip_stream ordered; the calls wait).
+ * gz_mlp_forward: y[n] = model(X[n x D]); bf16 != 0 rounds weights,
+ *   inputs and hidden activations to BF16 (FP32 accumulation).
+ * gz_mlp_loss_grad: *loss_host = mean((y - t)^2) of the FP32 forward pass and
+ *   grad[GZ_MLP_PARAMS] its gradient.
+ * gz_mlp_adam: one Adam step (bias-corrected, step >= 1) on params with
+ *   moment arrays m, v (same size).
+ */
+gz_status gz_mlp_forward(const float* params, const float* X, int32_t n, int32_t D,
+                         int32_t H, int32_t bf16, float* y, void* hip_stream);
+gz_status gz_mlp_loss_grad(const float* params, const float* X, const float* t,
+                           int32_t n, int32_t D, int32_t H, float* grad,
+                           float* loss_host, void* hip_stream);
+gz_status gz_mlp_adam(float* params, const float* grad, float* m, float* v,
+                      int32_t D, int32_t H, float lr, float beta1, float beta2,
+                      float eps, int32_t step, void* hip_stream);
+
 /* ------------------------------------------------------------------ errors */
 
 const char* gz_last_error(void);

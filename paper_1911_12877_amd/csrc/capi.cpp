@@ -81,10 +81,25 @@ gz_status finish_graph(gz_graph* g, uint32_t flags, hipStream_t st, gz_graph** o
   if (!(flags & GZ_GRAPH_NO_REINDEX)) graph_reindex(&g->host);
   graph_finish(&g->host);
   const HostGraph& h = g->host;
+  double sd = 0, sd2 = 0, sl = 0, sl2 = 0;
   for (int32_t v = 0; v < h.n; ++v) {
+    const double d = h.rowptr[v + 1] - h.rowptr[v], l = h.lo[v];
     g->max_deg = std::max(g->max_deg, h.rowptr[v + 1] - h.rowptr[v]);
     g->max_lo = std::max(g->max_lo, h.lo[v]);
+    sd += d;
+    sd2 += d * d;
+    sl += l;
+    sl2 += l * l;
   }
+  const double n = std::max<double>(h.n, 1);
+  g->stats[0] = h.n;
+  g->stats[1] = sd / 2;
+  g->stats[2] = sd / n;
+  g->stats[3] = sd > 0 ? sd2 / sd : 0;
+  g->stats[4] = g->max_deg;
+  g->stats[5] = sl / n;
+  g->stats[6] = sl > 0 ? sl2 / sl : 0;
+  g->stats[7] = g->max_lo;
   gz_status rc = upload_graph(g, st);
   if (rc) {
     release_graph(g);
@@ -181,6 +196,14 @@ gz_status build_schedule(const Pattern& p, int32_t induced, uint32_t flags,
 }
 
 }  // namespace
+
+namespace gz {
+bool read_pattern_checked(const uint8_t* adj, int32_t k, Pattern* p) { return read_pattern(adj, k, p); }
+gz_status build_schedule_for(const Pattern& p, int32_t induced, uint32_t flags, const int8_t* order,
+                             gz_schedule** out) {
+  return build_schedule(p, induced, flags, order, out);
+}
+}  // namespace gz
 
 extern "C" {
 

@@ -136,6 +136,9 @@ struct gz_graph {
   gz::HostGraph host;
   int32_t max_deg = 0;
   int32_t max_lo = 0;
+  // n, undirected edges, mean degree, E[d^2]/E[d], max degree, mean lo,
+  // E[lo^2]/E[lo], max lo (lo: neighbours with a smaller id)
+  double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int device = 0;
   int32_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;

@@ -28,7 +28,13 @@ GRAPH_NORMALIZE = 1
 GRAPH_NO_REINDEX = 2
 GRAPH_DEVICE_PTRS = 4
 SCHED_ANALYTIC = 0
+SCHED_LEARNED = 1
 SCHED_NO_RESTRICT = 8
+FEATURES = 108
+
+
+def mlp_param_count(D, H):
+    return H * D + 2 * H + 1
 
 
 class GzError(RuntimeError):
@@ -65,6 +71,13 @@ def _load():
         "gz_count_roots": [P, P, P, i64, P, P],
         "gz_count_bytes": [P, P, P, P, P],
         "gz_prepare_edges": [P, P, i64, i32, u32, P, P, P, P, P],
+        "gz_schedule_features": [P, P, i32, i32, P, P],
+        "gz_set_cost_model": [P, i32, i32],
+        "gz_compile_pattern_graph": [P, P, i32, i32, u32, P],
+        "gz_mlp_forward": [P, P, i32, i32, i32, i32, P, P],
+        "gz_mlp_loss_grad": [P, P, P, i32, i32, i32, P, P, P],
+        "gz_mlp_adam": [P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, i32, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -332,3 +345,63 @@ def count_bytes(g: Graph, s: Schedule, stream=None):
 
 def status_string(status: int) -> str:
     return _load().gz_status_string(status).decode()
+
+
+# ------------------------------------------------------- learned schedules
+
+
+def schedule_features(g: Graph, adj, order, induced=True):
+    """gz_schedule_features -> float32[FEATURES]."""
+    a, k = _adj_bytes(adj)
+    o = _np(order, np.int8)
+    out = np.zeros(FEATURES, dtype=np.float32)
+    _check(_load().gz_schedule_features(g.handle, a.ctypes.data, k, int(bool(induced)),
+                                        o.ctypes.data, out.ctypes.data))
+    return out
+
+
+def set_cost_model(params, H=None):
+    """gz_set_cost_model: install FP32 parameters (None removes the model)."""
+    if params is None:
+        _check(_load().gz_set_cost_model(None, FEATURES, 1))
+        return
+    p = _np(params, np.float32)
+    _check(_load().gz_set_cost_model(p.ctypes.data, FEATURES, H))
+
+
+def compile_pattern_graph(g: Graph, adj, induced=True, flags=SCHED_LEARNED) -> Schedule:
+    a, k = _adj_bytes(adj)
+    out = ctypes.c_void_p()
+    _check(_load().gz_compile_pattern_graph(g.handle, a.ctypes.data, k, int(bool(induced)), flags,
+                                            ctypes.byref(out)))
+    return Schedule(out.value)
+
+
+def _dptr(t):
+    assert _is_device_tensor(t) and t.dtype == torch.float32 and t.is_contiguous()
+    return t.data_ptr()
+
+
+def mlp_forward(params, X, H, bf16=False, stream=None):
+    """gz_mlp_forward on CUDA float32 tensors -> y (CUDA tensor)."""
+    n, D = X.shape
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(_load().gz_mlp_forward(_dptr(params), _dptr(X), n, D, H, int(bool(bf16)), _dptr(y),
+                                  _stream_ptr(stream)))
+    return y
+
+
+def mlp_loss_grad(params, X, t, H, stream=None):
+    """gz_mlp_loss_grad -> (loss, grad tensor)."""
+    n, D = X.shape
+    grad = torch.empty_like(params)
+    loss = ctypes.c_float()
+    _check(_load().gz_mlp_loss_grad(_dptr(params), _dptr(X), _dptr(t), n, D, H, _dptr(grad),
+                                    ctypes.byref(loss), _stream_ptr(stream)))
+    return float(loss.value), grad
+
+
+def mlp_adam(params, grad, m, v, D, H, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """gz_mlp_adam: one in-place Adam step."""
+    _check(_load().gz_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), D, H, lr, beta1,
+                               beta2, eps, step, _stream_ptr(stream)))

@@ -193,3 +193,40 @@ def test_pick_is_a_distinct_schedule():
         s, c = P.pick_schedule(a, True)
         assert s in P.distinct_schedules(a)
         assert c == min(P.analytic_cost(a, t, True) for t in P.distinct_schedules(a))
+
+
+# ------------------------------------------------ learned cost model oracle
+
+
+def test_mlp_oracle_gradient_finite_differences():
+    """The oracle's analytic gradient against central finite differences."""
+    import numpy as np
+    from oracle import mlp
+    rng = np.random.Generator(np.random.PCG64(3))
+    D, H, n = 7, 5, 11
+    P = rng.normal(0, 0.5, H * D + 2 * H + 1)
+    X = rng.normal(0, 1, (n, D))
+    t = rng.normal(0, 1, n)
+    loss, g = mlp.loss_grad(P, X, t, D, H)
+    eps = 1e-6
+    for i in range(P.size):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += eps
+        Pm[i] -= eps
+        fd = (mlp.loss_grad(Pp, X, t, D, H)[0] - mlp.loss_grad(Pm, X, t, D, H)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), i
+    # forward by hand for one sample
+    W1, b1, w2, b2 = mlp.unpack(P, D, H)
+    y0 = sum(w2[h] * max(0.0, float(W1[h] @ X[0] + b1[h])) for h in range(H)) + b2
+    assert abs(mlp.forward(P, X, D, H)[0][0] - y0) < 1e-12
+
+
+def test_bf16_rounding_oracle():
+    import numpy as np
+    from oracle import mlp
+    # exactly representable values stay; halfway cases go to even
+    assert mlp.bf16(np.array([1.0, -2.5, 0.0]))[0] == 1.0
+    one_plus = np.float32(1.0) + np.float32(2 ** -8)   # halfway between 1 and 1+2^-7
+    assert mlp.bf16(np.array([one_plus]))[0] == 1.0
+    up = np.float32(1.0) + np.float32(3 * 2 ** -9)     # nearer 1+2^-7
+    assert mlp.bf16(np.array([up]))[0] == 1.0 + 2 ** -7
