@@ -208,6 +208,18 @@ gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_bytes,
                          uint64_t* out_count);
 
+/*
+ * Clique schedules (K_k, 4 <= k <= 8) run on per-root bit rows: row p holds
+ * the bounded intersection of the loop after candidate p as a bit set over
+ * the root's candidates, and deeper loops AND rows and popcount the result.
+ * gz_count_ops runs that path instrumented and returns the number of 32-bit
+ * lane operations of those row intersections (each 64-bit row word ANDed
+ * costs 2, each 64-bit popcount 2) together with the count.  GZ_ENOTSUP for
+ * schedules that do not take the clique path.
+ */
+gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream,
+                       uint64_t* out_ops, uint64_t* out_count);
+
 /* ------------------------------------------------- learned schedule choice */
 
 /*

@@ -12,7 +12,7 @@ namespace gz {
 gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     const int32_t* roots, int64_t n_roots, uint64_t* per_root,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
-                    float* kernel_ms);
+                    float* kernel_ms, bool clique_ops = false);
 void free_graph_tasks(gz_graph* g);
 
 static thread_local std::string g_last_error;
@@ -481,6 +481,23 @@ gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s, void* hip_stre
     return GZ_EOVERFLOW;
   }
   if (out_bytes) *out_bytes = (uint64_t)bytes;
+  if (out_count) *out_count = (uint64_t)total;
+  return GZ_OK;
+}
+
+gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream,
+                       uint64_t* out_ops, uint64_t* out_count) {
+  gz_status rc = check_run(g, s);
+  if (rc) return rc;
+  unsigned __int128 total = 0, ops = 0;
+  rc = run_count(g, s, (hipStream_t)hip_stream, nullptr, 0, nullptr, false, &total, &ops, nullptr,
+                 true);
+  if (rc) return rc;
+  if ((total >> 64) || (ops >> 64)) {
+    set_error("count or operation total does not fit in 64 bits");
+    return GZ_EOVERFLOW;
+  }
+  if (out_ops) *out_ops = (uint64_t)ops;
   if (out_count) *out_count = (uint64_t)total;
   return GZ_OK;
 }

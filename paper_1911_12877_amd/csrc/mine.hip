@@ -478,13 +478,15 @@ struct CliqueWaveMem {
 // Cliques with D+1 more vertices inside AND(rows[ids[0..n)]) restricted to
 // words [0, nw): for D == 0 the popcount, otherwise a sum over the set's
 // members b, descending into rows[b] (whose bits all lie below b).
-template <int D>
+template <int D, bool IN>
 __device__ unsigned long long cl_count(const unsigned long long* rows, int W, int (&ids)[8],
-                                       int n, int nw) {
+                                       int n, int nw, unsigned long long& ops) {
   unsigned long long total = 0;
   for (int w = 0; w < nw; ++w) {
     unsigned long long s = ~0ull;
     for (int t = 0; t < n; ++t) s &= rows[ids[t] * W + w];
+    // instrumented: 32-bit lane ops of this word's ANDs and final popcount
+    if (IN) ops += 2ull * (unsigned)(n - 1) + (D == 0 ? 2ull : 0ull);
     if constexpr (D == 0) {
       total += (unsigned long long)__popcll(s);
     } else {
@@ -492,7 +494,7 @@ __device__ unsigned long long cl_count(const unsigned long long* rows, int W, in
         const int b = w * 64 + __builtin_ctzll(s);
         s &= s - 1;
         ids[n] = b;
-        total += cl_count<D - 1>(rows, W, ids, n + 1, w + 1);
+        total += cl_count<D - 1, IN>(rows, W, ids, n + 1, w + 1, ops);
       }
     }
   }
@@ -501,9 +503,9 @@ __device__ unsigned long long cl_count(const unsigned long long* rows, int W, in
 
 // K-cliques of the root that take C1[a] as their second vertex and a member
 // of word w of row a as their third
-template <int K>
+template <int K, bool IN>
 __device__ __forceinline__ unsigned long long clique_unit(const unsigned long long* rows, int W,
-                                                         int a, int w) {
+                                                         int a, int w, unsigned long long& ops) {
   int ids[8];
   ids[0] = a;
   unsigned long long s = rows[a * W + w];
@@ -512,7 +514,7 @@ __device__ __forceinline__ unsigned long long clique_unit(const unsigned long lo
     const int b = w * 64 + __builtin_ctzll(s);
     s &= s - 1;
     ids[1] = b;
-    total += cl_count<K - 4>(rows, W, ids, 2, w + 1);
+    total += cl_count<K - 4, IN>(rows, W, ids, 2, w + 1, ops);
   }
   return total;
 }
@@ -539,12 +541,12 @@ __device__ __forceinline__ int row_probe(const Graph& g, const int32_t* xs, int 
 }
 
 // Wave path: roots with at most 64 candidates.
-template <int K, bool PER_ROOT>
+template <int K, bool PER_ROOT, bool IN>
 __global__ __launch_bounds__(BLOCK) void k_clique_wave(Graph g, RootList L, Out o, int batch) {
   __shared__ CliqueWaveMem mem[WPB];
   CliqueWaveMem& M = mem[threadIdx.x / WAVE];
   const int lane = lane_id();
-  unsigned long long cnt = 0;
+  unsigned long long cnt = 0, ops = 0;
   for (;;) {
     long long t0 = 0;
     if (lane == 0) t0 = (long long)atomicAdd(o.acc + 4, (unsigned long long)batch);
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(BLOCK) void k_clique_wave(Graph g, RootList L, Out 
           }
         }
         wave_sync();
-        if (lane < d) cnt += clique_unit<K>(M.rows, 1, lane, 0);
+        if (lane < d) cnt += clique_unit<K, IN>(M.rows, 1, lane, 0, ops);
         wave_sync();
       }
       if constexpr (PER_ROOT) {
@@ -598,12 +600,17 @@ __global__ __launch_bounds__(BLOCK) void k_clique_wave(Graph g, RootList L, Out 
     wave_sum_u128(cnt, &l, &h);
     if (lane == 0 && (l | h)) add_u128(o.acc, l, h);
   }
+  if constexpr (IN) {
+    unsigned long long l, h;
+    wave_sum_u128(ops, &l, &h);
+    if (lane == 0 && (l | h)) add_u128(o.acc + 2, l, h);
+  }
 }
 
 // Workgroup path: roots with more than 64 candidates (at most 64 W).
 // Dynamic LDS: rows[S*W] (64-bit) then xs, pref, urs, ulen, slot (S int32
 // each), S = 64 W.
-template <int K, bool PER_ROOT>
+template <int K, bool PER_ROOT, bool IN>
 __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Out o, int W) {
   extern __shared__ unsigned long long dyn[];
   __shared__ int s_task;
@@ -618,7 +625,7 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / WAVE;
-  unsigned long long cnt = 0;
+  unsigned long long cnt = 0, ops = 0;
   for (;;) {
     if (tid == 0) s_task = (int)atomicAdd(o.acc + 7, 1ull);
     __syncthreads();
@@ -677,7 +684,7 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
     unsigned long long mine = 0;
     for (int q = tid; q < d * Wd; q += CBLOCK) {
       const int a = q / Wd, w = q - a * Wd;
-      if (w * 64 < a) mine += clique_unit<K>(rows, W, a, w);
+      if (w * 64 < a) mine += clique_unit<K, IN>(rows, W, a, w, ops);
     }
     if constexpr (PER_ROOT) {
       unsigned long long l, h;
@@ -695,6 +702,11 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
     unsigned long long l, h;
     wave_sum_u128(cnt, &l, &h);
     if (lane == 0 && (l | h)) add_u128(o.acc, l, h);
+  }
+  if constexpr (IN) {
+    unsigned long long l, h;
+    wave_sum_u128(ops, &l, &h);
+    if (lane == 0 && (l | h)) add_u128(o.acc + 2, l, h);
   }
 }
 
@@ -817,7 +829,7 @@ void free_clique_lists(CliqueLists* c) {
   *c = CliqueLists();
 }
 
-template <int K, bool PR>
+template <int K, bool PR, bool IN>
 gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::Out& o,
                           hipStream_t st) {
   int devid = 0, cus = 0, per_cu = 0;
@@ -825,7 +837,7 @@ gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::
   GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
   if (C.n_light > 0) {
     const int batch = 8;
-    auto kw = dev::k_clique_wave<K, PR>;
+    auto kw = dev::k_clique_wave<K, PR, IN>;
     GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kw, dev::BLOCK, 0));
     long long blocks = (long long)std::max(per_cu, 1) * std::max(cus, 1);
     long long need = (C.n_light + (long long)batch * dev::WPB - 1) / ((long long)batch * dev::WPB);
@@ -835,7 +847,7 @@ gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::
     GZ_HIP(hipGetLastError());
   }
   if (C.n_heavy > 0) {
-    auto kb = dev::k_clique_block<K, PR>;
+    auto kb = dev::k_clique_block<K, PR, IN>;
     const int W = (C.heavy_max_lo + 63) / 64;
     const size_t S = 64 * (size_t)W;
     const size_t lds = S * W * sizeof(unsigned long long) + 5 * S * sizeof(int32_t);
@@ -854,15 +866,15 @@ gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::
   return GZ_OK;
 }
 
-template <bool PR>
+template <bool PR, bool IN>
 gz_status launch_clique(int k, const dev::Graph& g, const CliqueLists& C, const dev::Out& o,
                         hipStream_t st) {
   switch (k) {
-    case 4: return launch_clique_k<4, PR>(g, C, o, st);
-    case 5: return launch_clique_k<5, PR>(g, C, o, st);
-    case 6: return launch_clique_k<6, PR>(g, C, o, st);
-    case 7: return launch_clique_k<7, PR>(g, C, o, st);
-    case 8: return launch_clique_k<8, PR>(g, C, o, st);
+    case 4: return launch_clique_k<4, PR, IN>(g, C, o, st);
+    case 5: return launch_clique_k<5, PR, IN>(g, C, o, st);
+    case 6: return launch_clique_k<6, PR, IN>(g, C, o, st);
+    case 7: return launch_clique_k<7, PR, IN>(g, C, o, st);
+    case 8: return launch_clique_k<8, PR, IN>(g, C, o, st);
     default:
       set_error("clique path needs 4 <= k <= 8");
       return GZ_EINVAL;
@@ -918,7 +930,7 @@ static gz_status graph_tasks(const gz_graph* g, bool bounded1, int chunk,
 gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     const int32_t* roots, int64_t n_roots, uint64_t* per_root,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
-                    float* kernel_ms) {
+                    float* kernel_ms, bool clique_ops) {
   const Plan& plan = s->plan;
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
@@ -960,6 +972,10 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   }
   // clique fast path: K_k (k >= 4) with chain bounds, rows of at most 16 words
   const bool use_clique = !instr && plan.k >= 4 && is_clique_chain(plan) && g->max_lo <= 1024;
+  if (clique_ops && (!use_clique || pr)) {
+    set_error("operation counts exist only for the clique path over all roots");
+    return GZ_ENOTSUP;
+  }
   CliqueLists own_lists;
   const CliqueLists* lists = nullptr;
   if (!rc && use_clique) {
@@ -993,8 +1009,9 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
     if (!rc && tasks.n_tasks > 0) {
       if (use_clique) {
-        rc = pr ? launch_clique<true>(plan.k, dg, *lists, o, st)
-                : launch_clique<false>(plan.k, dg, *lists, o, st);
+        rc = pr ? launch_clique<true, false>(plan.k, dg, *lists, o, st)
+                : (clique_ops ? launch_clique<false, true>(plan.k, dg, *lists, o, st)
+                              : launch_clique<false, false>(plan.k, dg, *lists, o, st));
       } else if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
       else if (pr) rc = launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
       else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
@@ -1027,7 +1044,9 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   if (rc) return rc;
 
   *total = ((unsigned __int128)hacc[1] << 64) | hacc[0];
-  if (bytes) {
+  if (bytes && clique_ops) {
+    *bytes = ((unsigned __int128)hacc[3] << 64) | hacc[2];
+  } else if (bytes) {
     unsigned __int128 b = ((unsigned __int128)hacc[3] << 64) | hacc[2];
     // loop 1 is evaluated once per root: one list, N(v0), below its bound
     for (int64_t i = 0; i < nr; ++i) {

@@ -70,6 +70,7 @@ def _load():
         "gz_count_timed": [P, P, P, P, P],
         "gz_count_roots": [P, P, P, i64, P, P],
         "gz_count_bytes": [P, P, P, P, P],
+        "gz_count_ops": [P, P, P, P, P],
         "gz_prepare_edges": [P, P, i64, i32, u32, P, P, P, P, P],
         "gz_schedule_features": [P, P, i32, i32, P, P],
         "gz_set_cost_model": [P, i32, i32],
@@ -341,6 +342,14 @@ def count_bytes(g: Graph, s: Schedule, stream=None):
     _check(_load().gz_count_bytes(g.handle, s.handle, _stream_ptr(stream), ctypes.byref(b),
                                   ctypes.byref(c)))
     return int(b.value), int(c.value)
+
+
+def count_ops(g: Graph, s: Schedule, stream=None):
+    """(bit-row intersection lane operations, count) of the clique path."""
+    o, c = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_load().gz_count_ops(g.handle, s.handle, _stream_ptr(stream), ctypes.byref(o),
+                                ctypes.byref(c)))
+    return int(o.value), int(c.value)
 
 
 def status_string(status: int) -> str:

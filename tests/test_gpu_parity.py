@@ -270,3 +270,46 @@ def test_clique_paths_vs_oracle(which):
         _, per = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
                               roots=roots, per_root=True)
         assert np.array_equal(gz.count_roots(G, s, roots), per), (which, k)
+
+
+def _clique_ops_complete(n, k):
+    """Lane operations of the bit-row intersections for K_k on K_n, from the
+    definition: after reindexing vertex v has lo = v candidates and every row
+    is full (row p = bits 0..p-1).  A row-word intersection of r rows costs
+    2(r-1); the last level adds 2 for the popcount."""
+    import functools
+
+    def words(p):  # words holding bits below p
+        return (p + 63) // 64
+
+    @functools.lru_cache(maxsize=None)
+    def cl_w(depth, r, b, nw):
+        # the AND of r rows including row b (bits < b), over words [0, nw)
+        ops = 0
+        for w in range(nw):
+            ops += 2 * (r - 1) + (2 if depth == 0 else 0)
+            if depth > 0:
+                for c in range(64 * w, min(64 * w + 64, b)):
+                    ops += cl_w(depth - 1, r + 1, c, w + 1)
+        return ops
+
+    total = 0
+    for d in range(k - 1, n):  # roots with fewer than k-1 candidates are skipped
+        for a in range(d):
+            for w in range(words(a)):
+                for b in range(64 * w, min(64 * w + 64, a)):
+                    total += cl_w(k - 4, 2, b, w + 1)
+    return total
+
+
+def test_clique_op_count_definition():
+    for n, k in ((30, 4), (30, 5), (90, 4), (70, 5)):
+        G = gz.load_edges(*synth.complete_edges(n))
+        s = gz.compile_pattern(P.named(f"k{k}"), True)
+        ops, c = gz.count_ops(G, s)
+        assert c == math.comb(n, k)
+        assert ops == _clique_ops_complete(n, k), (n, k)
+    G = gz.load_edges(*synth.cycle_edges(10))
+    with pytest.raises(gz.GzError) as ex:
+        gz.count_ops(G, gz.compile_pattern(P.named("c4"), True))
+    assert ex.value.status == gz.GZ_ENOTSUP
