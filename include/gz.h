@@ -220,6 +220,38 @@ gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
 gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                        uint64_t* out_ops, uint64_t* out_count);
 
+/* ------------------------------------------------------------ motif census */
+
+/*
+ * Batched counting of many patterns (k <= 5) over many graphs in one
+ * persistent launch: every (graph, pattern, first-loop task) item is handed
+ * out from one queue, and each (graph, pattern) pair keeps its own 128-bit
+ * count.  The zeroing of the accumulators and the launch are captured once
+ * into a HIP graph and replayed by gz_census_run.  Graph and schedule
+ * handles must outlive the census object; counts follow the order
+ * counts[graph * n_scheds + sched].  The census runs on its own stream and
+ * each call returns when its work is done.
+ */
+typedef struct gz_census gz_census;
+
+gz_status gz_census_create(const gz_graph* const* graphs, int32_t n_graphs,
+                           const gz_schedule* const* scheds, int32_t n_scheds,
+                           gz_census** out);
+
+/* One replay; counts[n_graphs * n_scheds] (may be NULL) and the replay's
+ * device time in milliseconds (may be NULL).  GZ_EOVERFLOW if a count does
+ * not fit in 64 bits. */
+gz_status gz_census_run(gz_census* c, uint64_t* counts, float* ms);
+
+/* Autotune the launch: task granularity (first-loop candidates per item) of
+ * 3-vertex patterns and of larger ones, and items per queue pop.  Each
+ * candidate is rebuilt, captured and replayed twice; the fastest is kept.
+ * params[3] receives (granularity k=3, granularity k>=4, items per pop),
+ * best_ms its replay time.  Either may be NULL. */
+gz_status gz_census_tune(gz_census* c, int32_t* params, float* best_ms);
+
+void gz_census_free(gz_census* c);
+
 /* ------------------------------------------------- learned schedule choice */
 
 /*

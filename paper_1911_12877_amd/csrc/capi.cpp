@@ -15,6 +15,12 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     float* kernel_ms, bool clique_ops = false);
 void free_graph_tasks(gz_graph* g);
 
+gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
+                        const gz_schedule* const* scheds, int32_t n_scheds, void** out);
+gz_status census_run(void* c, uint64_t* counts, float* ms);
+gz_status census_tune(void* c, int32_t* params, float* best_ms);
+void census_free(void* c);
+
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -501,6 +507,29 @@ gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream
   if (out_count) *out_count = (uint64_t)total;
   return GZ_OK;
 }
+
+gz_status gz_census_create(const gz_graph* const* graphs, int32_t n_graphs,
+                           const gz_schedule* const* scheds, int32_t n_scheds, gz_census** out) {
+  return census_create(graphs, n_graphs, scheds, n_scheds, (void**)out);
+}
+
+gz_status gz_census_run(gz_census* c, uint64_t* counts, float* ms) {
+  if (!c) {
+    set_error("NULL census");
+    return GZ_EINVAL;
+  }
+  return census_run(c, counts, ms);
+}
+
+gz_status gz_census_tune(gz_census* c, int32_t* params, float* best_ms) {
+  if (!c) {
+    set_error("NULL census");
+    return GZ_EINVAL;
+  }
+  return census_tune(c, params, best_ms);
+}
+
+void gz_census_free(gz_census* c) { census_free(c); }
 
 const char* gz_last_error(void) { return g_last_error.c_str(); }
 

@@ -710,6 +710,114 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
   }
 }
 
+// ------------------------------------------------------------------ census
+//
+// Motif census: one persistent launch over (graph, pattern, task) items of
+// many graphs and many patterns (k <= 5).  Item t names a (graph, pattern)
+// pair through an exclusive prefix over the pairs' task counts, then a
+// first-loop task of that pair through the graph's own task prefix; the
+// task runs the same loops as k_mine and its count is added to the pair's
+// 128-bit accumulator.
+
+struct CensusPair {
+  const int64_t* prefix;  // first-loop task prefix of the pair's graph (n + 1)
+  int32_t graph;          // index into the graph table
+  int32_t plan;           // index into the plan table
+  int32_t chunk;
+  int32_t bounded1;
+};
+
+struct CensusArgs {
+  const Graph* graphs;
+  const Plan* plans;
+  const CensusPair* pairs;
+  const long long* pair_prefix;  // n_pairs + 1
+  int n_pairs;
+  int batch;
+  unsigned long long* counts;    // 2 per pair, then the queue head
+};
+
+// one wave's LDS, whatever pattern size its current task has (waves of a
+// workgroup may run tasks of different sizes at the same time)
+union CensusWaveMem {
+  WaveMem<2> m2;
+  WaveMem<3> m3;
+  WaveMem<4> m4;
+  WaveMem<5> m5;
+};
+
+template <int K>
+__device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
+                            const CensusPair& pr, long long local, Acc& acc) {
+  const int lane = lane_id();
+  long long lo = 0, hi = (long long)g.n + 1;
+  while (lo < hi) {
+    long long mid = (lo + hi) >> 1;
+    if (pr.prefix[mid] <= local) lo = mid + 1; else hi = mid;
+  }
+  const int32_t v0 = uni((int32_t)(lo - 1));
+  const int32_t rs0 = uni(g.rowptr[v0]);
+  const int32_t rd0 = uni(g.rowptr[v0 + 1]) - rs0;
+  const int32_t len1 = pr.bounded1 ? uni(g.lo[v0]) : rd0;
+  const int32_t begin = (int32_t)(local - pr.prefix[v0]) * pr.chunk;
+  const int32_t end = min(begin + pr.chunk, len1);
+  int32_t v[K], rs[K], rd[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = rs[j] = rd[j] = 0;
+  v[0] = v0;
+  rs[0] = rs0;
+  rd[0] = rd0;
+  if constexpr (K == 2) {
+    if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
+  } else if constexpr (K == 3) {
+    last_level<K, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin, begin, acc);
+  } else {
+    for (int32_t i = begin; i < end; ++i) {
+      v[1] = uni(g.col[rs0 + i]);
+      rs[1] = uni(g.rowptr[v[1]]);
+      rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
+      mat_level<K, 2, false>(g, plan, M, v, rs, rd, 0u, i, acc);
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_census(CensusArgs A) {
+  __shared__ CensusWaveMem mem[WPB];
+  CensusWaveMem& M = mem[threadIdx.x / WAVE];
+  const int lane = lane_id();
+  unsigned long long* queue = A.counts + 2 * (long long)A.n_pairs;
+  const long long n_tasks = A.pair_prefix[A.n_pairs];
+  for (;;) {
+    long long t0 = 0;
+    if (lane == 0) t0 = (long long)atomicAdd(queue, (unsigned long long)A.batch);
+    t0 = __shfl(t0, 0, WAVE);
+    if (t0 >= n_tasks) break;
+    const long long t1 = min(t0 + (long long)A.batch, n_tasks);
+    for (long long t = t0; t < t1; ++t) {
+      int lo = 0, hi = A.n_pairs + 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (A.pair_prefix[mid] <= t) lo = mid + 1; else hi = mid;
+      }
+      const int pi = lo - 1;
+      const CensusPair pr = A.pairs[pi];
+      const Graph g = A.graphs[pr.graph];
+      const Plan& plan = A.plans[pr.plan];
+      const long long local = t - A.pair_prefix[pi];
+      Acc acc{0ull, 0ull};
+      switch (plan.k) {
+        case 2: census_task<2>(g, plan, M.m2, pr, local, acc); break;
+        case 3: census_task<3>(g, plan, M.m3, pr, local, acc); break;
+        case 4: census_task<4>(g, plan, M.m4, pr, local, acc); break;
+        default: census_task<5>(g, plan, M.m5, pr, local, acc); break;
+      }
+      unsigned long long l, h;
+      wave_sum_u128(acc.cnt, &l, &h);
+      if (lane == 0 && (l | h)) add_u128(A.counts + 2 * (long long)pi, l, h);
+    }
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0ull;
@@ -1062,6 +1170,230 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
     for (int64_t i = 0; i < nr; ++i) per_root[i] = hacc[8 + i];
   }
+  return GZ_OK;
+}
+
+
+// ------------------------------------------------------------ census host
+
+void census_free(void* p);
+
+struct gz_census_impl {
+  std::vector<const gz_graph*> graphs;
+  std::vector<const gz_schedule*> scheds;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  dev::Graph* d_graphs = nullptr;
+  Plan* d_plans = nullptr;
+  dev::CensusPair* d_pairs = nullptr;
+  long long* d_pair_prefix = nullptr;
+  unsigned long long* d_counts = nullptr;
+  int n_pairs = 0;
+  long long n_tasks = 0;
+  int chunk3 = 64, chunk45 = 16, batch = 1;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void census_release_tables(gz_census_impl* c) {
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->exec = nullptr;
+  c->graph = nullptr;
+  if (c->d_pairs) (void)hipFree(c->d_pairs);
+  if (c->d_pair_prefix) (void)hipFree(c->d_pair_prefix);
+  c->d_pairs = nullptr;
+  c->d_pair_prefix = nullptr;
+}
+
+// Pair table and prefix for the current tuning, then capture the zeroing of
+// the accumulators and the census launch into a HIP graph.
+static gz_status census_build(gz_census_impl* c) {
+  census_release_tables(c);
+  const int ng = (int)c->graphs.size(), ns = (int)c->scheds.size();
+  std::vector<dev::CensusPair> pairs((size_t)ng * ns);
+  std::vector<long long> prefix((size_t)ng * ns + 1, 0);
+  for (int gi = 0; gi < ng; ++gi)
+    for (int si = 0; si < ns; ++si) {
+      const Plan& pl = c->scheds[si]->plan;
+      const bool b1 = pl.lv[1].bound == 0;
+      const int chunk = pl.k <= 2 ? (1 << 30) : (pl.k == 3 ? c->chunk3 : c->chunk45);
+      DevTasks dt;
+      gz_status rc = graph_tasks(c->graphs[gi], b1, chunk, c->stream, &dt);
+      if (rc) return rc;
+      const int pi = gi * ns + si;
+      pairs[pi] = dev::CensusPair{dt.prefix, gi, si, chunk, b1 ? 1 : 0};
+      prefix[pi + 1] = prefix[pi] + dt.n_tasks;
+    }
+  c->n_pairs = ng * ns;
+  c->n_tasks = prefix.back();
+  GZ_HIP(hipMalloc(&c->d_pairs, sizeof(dev::CensusPair) * pairs.size()));
+  GZ_HIP(hipMalloc(&c->d_pair_prefix, sizeof(long long) * prefix.size()));
+  GZ_HIP(hipMemcpy(c->d_pairs, pairs.data(), sizeof(dev::CensusPair) * pairs.size(),
+                   hipMemcpyHostToDevice));
+  GZ_HIP(hipMemcpy(c->d_pair_prefix, prefix.data(), sizeof(long long) * prefix.size(),
+                   hipMemcpyHostToDevice));
+  int per_cu = 0, cus = 0;
+  GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::k_census, dev::BLOCK, 0));
+  GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  long long need = (c->n_tasks + (long long)c->batch * dev::WPB - 1) / ((long long)c->batch * dev::WPB);
+  c->grid = (int)std::max(1ll, std::min((long long)std::max(per_cu, 1) * std::max(cus, 1), need));
+  const long long n_acc = 2LL * c->n_pairs + 1;
+  dev::CensusArgs args{c->d_graphs, c->d_plans, c->d_pairs, c->d_pair_prefix, c->n_pairs,
+                       c->batch, c->d_counts};
+  GZ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
+                     dim3(256), 0, c->stream, c->d_counts, n_acc);
+  if (c->n_tasks > 0)
+    hipLaunchKernelGGL(dev::k_census, dim3((unsigned)c->grid), dim3(dev::BLOCK), 0, c->stream, args);
+  hipError_t e = hipStreamEndCapture(c->stream, &c->graph);
+  if (e != hipSuccess) {
+    set_error(std::string("census graph capture: ") + hipGetErrorString(e));
+    return GZ_EDEVICE;
+  }
+  GZ_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+  return GZ_OK;
+}
+
+static gz_status census_launch(gz_census_impl* c, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GZ_HIP(hipEventCreate(&e0));
+  GZ_HIP(hipEventCreate(&e1));
+  gz_status rc = GZ_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess || hipGraphLaunch(c->exec, c->stream) != hipSuccess ||
+      hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(ms, e0, e1) != hipSuccess) {
+    set_error("census launch failed");
+    rc = GZ_EDEVICE;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
+                        const gz_schedule* const* scheds, int32_t n_scheds, void** out) {
+  if (!out || n_graphs < 1 || n_scheds < 1 || !graphs || !scheds) {
+    set_error("bad census arguments");
+    return GZ_EINVAL;
+  }
+  auto* c = new (std::nothrow) gz_census_impl();
+  if (!c) {
+    set_error("out of host memory");
+    return GZ_ENOMEM;
+  }
+  gz_status rc = GZ_OK;
+  if (hipGetDevice(&c->device) != hipSuccess) rc = GZ_EDEVICE;
+  for (int i = 0; i < n_graphs && !rc; ++i) {
+    if (!graphs[i] || graphs[i]->device != c->device) {
+      set_error("census graphs must be loaded on the current device");
+      rc = GZ_EINVAL;
+    }
+  }
+  for (int i = 0; i < n_scheds && !rc; ++i) {
+    if (!scheds[i] || scheds[i]->plan.k > 5) {
+      set_error("census patterns must have at most 5 vertices");
+      rc = scheds[i] ? GZ_ENOTSUP : GZ_EINVAL;
+    }
+  }
+  if (!rc) {
+    c->graphs.assign(graphs, graphs + n_graphs);
+    c->scheds.assign(scheds, scheds + n_scheds);
+    std::vector<dev::Graph> gt;
+    for (const gz_graph* g : c->graphs) gt.push_back(dev::Graph{g->d_rowptr, g->d_col, g->d_lo, g->host.n});
+    std::vector<Plan> pt;
+    for (const gz_schedule* s : c->scheds) pt.push_back(s->plan);
+    if (hipStreamCreate(&c->stream) != hipSuccess ||
+        hipMalloc(&c->d_graphs, sizeof(dev::Graph) * gt.size()) != hipSuccess ||
+        hipMalloc(&c->d_plans, sizeof(Plan) * pt.size()) != hipSuccess ||
+        hipMalloc(&c->d_counts, sizeof(unsigned long long) * (2 * (size_t)n_graphs * n_scheds + 1)) !=
+            hipSuccess ||
+        hipMemcpy(c->d_graphs, gt.data(), sizeof(dev::Graph) * gt.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c->d_plans, pt.data(), sizeof(Plan) * pt.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("census device set-up failed");
+      rc = GZ_EDEVICE;
+    }
+  }
+  if (!rc) rc = census_build(c);
+  if (rc) {
+    census_free(c);
+    return rc;
+  }
+  *out = c;
+  return GZ_OK;
+}
+
+void census_free(void* p) {
+  auto* c = (gz_census_impl*)p;
+  if (!c) return;
+  census_release_tables(c);
+  for (void* q : {(void*)c->d_graphs, (void*)c->d_plans, (void*)c->d_counts})
+    if (q) (void)hipFree(q);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+gz_status census_run(void* p, uint64_t* counts, float* ms) {
+  auto* c = (gz_census_impl*)p;
+  float t = 0.0f;
+  gz_status rc = census_launch(c, &t);
+  if (rc) return rc;
+  std::vector<unsigned long long> h(2 * (size_t)c->n_pairs);
+  GZ_HIP(hipMemcpy(h.data(), c->d_counts, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i < c->n_pairs; ++i) {
+    if (h[2 * i + 1]) {
+      set_error("a census count does not fit in 64 bits");
+      return GZ_EOVERFLOW;
+    }
+    if (counts) counts[i] = h[2 * i];
+  }
+  if (ms) *ms = t;
+  return GZ_OK;
+}
+
+// Autotuning: task granularity of 3-vertex patterns and of larger ones, and
+// tasks per queue pop; each candidate is rebuilt, captured and replayed
+// twice, the fastest kept.
+gz_status census_tune(void* p, int32_t* params, float* best_ms) {
+  auto* c = (gz_census_impl*)p;
+  const int c3s[] = {32, 128};
+  const int c45s[] = {4, 16, 64};
+  const int batches[] = {1, 4};
+  float best = -1.0f;
+  int b3 = c->chunk3, b45 = c->chunk45, bb = c->batch;
+  for (int x3 : c3s)
+    for (int x45 : c45s)
+      for (int xb : batches) {
+        c->chunk3 = x3;
+        c->chunk45 = x45;
+        c->batch = xb;
+        gz_status rc = census_build(c);
+        if (rc) return rc;
+        float t1 = 0.0f, t2 = 0.0f;
+        rc = census_launch(c, &t1);
+        if (!rc) rc = census_launch(c, &t2);
+        if (rc) return rc;
+        const float t = std::min(t1, t2);
+        if (best < 0.0f || t < best) {
+          best = t;
+          b3 = x3;
+          b45 = x45;
+          bb = xb;
+        }
+      }
+  c->chunk3 = b3;
+  c->chunk45 = b45;
+  c->batch = bb;
+  gz_status rc = census_build(c);
+  if (rc) return rc;
+  if (params) {
+    params[0] = b3;
+    params[1] = b45;
+    params[2] = bb;
+  }
+  if (best_ms) *best_ms = best;
   return GZ_OK;
 }
 

@@ -71,6 +71,9 @@ def _load():
         "gz_count_roots": [P, P, P, i64, P, P],
         "gz_count_bytes": [P, P, P, P, P],
         "gz_count_ops": [P, P, P, P, P],
+        "gz_census_create": [P, i32, P, i32, P],
+        "gz_census_run": [P, P, P],
+        "gz_census_tune": [P, P, P],
         "gz_prepare_edges": [P, P, i64, i32, u32, P, P, P, P, P],
         "gz_schedule_features": [P, P, i32, i32, P, P],
         "gz_set_cost_model": [P, i32, i32],
@@ -88,6 +91,8 @@ def _load():
     lib.gz_free_graph.restype = None
     lib.gz_free_schedule.argtypes = [P]
     lib.gz_free_schedule.restype = None
+    lib.gz_census_free.argtypes = [P]
+    lib.gz_census_free.restype = None
     lib.gz_last_error.argtypes = []
     lib.gz_last_error.restype = ctypes.c_char_p
     lib.gz_status_string.argtypes = [ctypes.c_int32]
@@ -414,3 +419,46 @@ def mlp_adam(params, grad, m, v, D, H, lr, step, beta1=0.9, beta2=0.999, eps=1e-
     """gz_mlp_adam: one in-place Adam step."""
     _check(_load().gz_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), D, H, lr, beta1,
                                beta2, eps, step, _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------------ census
+
+
+class Census:
+    """gz_census: many patterns over many graphs in one captured launch.
+    Keeps references to its graphs and schedules."""
+
+    def __init__(self, graphs, scheds):
+        self.graphs = list(graphs)
+        self.scheds = list(scheds)
+        G = (ctypes.c_void_p * len(self.graphs))(*[g.handle.value for g in self.graphs])
+        S = (ctypes.c_void_p * len(self.scheds))(*[s.handle.value for s in self.scheds])
+        out = ctypes.c_void_p()
+        _check(_load().gz_census_create(G, len(self.graphs), S, len(self.scheds),
+                                        ctypes.byref(out)))
+        self._h = out
+
+    def run(self):
+        """-> (counts uint64[n_graphs, n_scheds], device ms)."""
+        c = np.zeros(len(self.graphs) * len(self.scheds), dtype=np.uint64)
+        ms = ctypes.c_float()
+        _check(_load().gz_census_run(self._h, c.ctypes.data, ctypes.byref(ms)))
+        return c.reshape(len(self.graphs), len(self.scheds)), float(ms.value)
+
+    def tune(self):
+        """-> ((granularity k=3, granularity k>=4, items per pop), best ms)."""
+        p = np.zeros(3, dtype=np.int32)
+        ms = ctypes.c_float()
+        _check(_load().gz_census_tune(self._h, p.ctypes.data, ctypes.byref(ms)))
+        return tuple(int(x) for x in p), float(ms.value)
+
+    def close(self):
+        if self._h and self._h.value:
+            _load().gz_census_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
