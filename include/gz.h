@@ -170,17 +170,25 @@ void gz_free_schedule(gz_schedule* s);
 /*
  * Exact number of instances of the compiled pattern in the graph (each
  * instance once; |Aut(P)| times that with GZ_SCHED_NO_RESTRICT).  Runs the
- * mining kernels on hip_stream and waits for them.  Errors: GZ_EINVAL (NULL
- * handle), GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified),
+ * mining kernels on hip_stream and waits for them.  Patterns of k >= 4 that
+ * take the generic loops run in two phases: prefixes whose loop base is
+ * longer than a threshold (2048 elements; the environment variable
+ * GZ_SPLIT_MIN_LEN, a decimal integer >= 0, overrides it) are recorded by
+ * the first launch and expanded in 256-element pieces by a second; the host
+ * reads the record count in between.  The record list holds 2^20 prefixes
+ * (GZ_SPLIT_CAP, 1..2^26, overrides it); prefixes met after it fills are
+ * expanded in place.  Invalid override values are ignored.  Errors: GZ_EINVAL (NULL handle),
+ * GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified), GZ_ENOMEM,
  * GZ_EDEVICE.
  */
 gz_status gz_count(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                    uint64_t* out_count);
 
 /*
- * gz_count that also reports the mining kernel's own duration in
- * milliseconds, measured with HIP events recorded on hip_stream around that
- * launch (accumulator set-up and the result copy are outside the interval).
+ * gz_count that also reports the mining kernels' own duration in
+ * milliseconds, measured with HIP events recorded on hip_stream around the
+ * mining launches (both phases and the read-back between them; accumulator
+ * set-up and the result copy are outside the interval).
  */
 gz_status gz_count_timed(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_count,

@@ -20,7 +20,14 @@
 // laid out one per lane, their base lengths prefix-summed, and every lane
 // then takes one (item, base element) pair at a time, so short lists still
 // fill the wave.
+//
+// A prefix whose loop base is longer than a threshold is not expanded by the
+// wave that meets it: the wave records it and moves on, and a second launch
+// hands the recorded bases out in CH-element pieces, one wave per piece, so a
+// hub's list no longer serialises its whole subtree on one wave.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 
 #include "gz_internal.h"
 
@@ -41,6 +48,8 @@ struct Graph {
   int32_t n;
 };
 
+struct HeavyItem;
+
 struct Tasks {
   const int64_t* __restrict__ prefix;  // n_roots + 1
   const int32_t* __restrict__ roots;   // nullptr: root r is vertex r
@@ -49,7 +58,9 @@ struct Tasks {
   int32_t chunk;
   int32_t bounded1;                    // loop 1 bounded by v0
   int32_t batch;                       // tasks per queue pop
-  int32_t pad;
+  int32_t heavy_min;                   // split loop bases longer than this
+  HeavyItem* heavy;                    // second-phase list (nullptr: no split)
+  long long heavy_cap;
 };
 
 // acc[0..1]: 128-bit count; acc[2..3]: 128-bit bytes; acc[4]: queue head;
@@ -265,10 +276,29 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 
 // ---------------------------------------------------- materialised loops
 
+// A prefix (v_0..v_{I-1}) whose loop-I base is long is not expanded by the
+// wave that meets it; it is recorded and its base later handed out in
+// CH-element pieces, one wave per piece (second phase).
+struct HeavyItem {
+  int32_t v[kMaxK - 1];
+  int32_t level;
+  int32_t r;         // root slot (per-root mode)
+  int32_t base_len;
+};
+
+struct Split {
+  HeavyItem* items;              // nullptr: never split
+  unsigned long long* n_items;   // atomic count (may exceed cap: then not split)
+  long long cap;
+  int min_len;                   // split bases longer than this
+  int32_t r;                     // current root slot
+};
+
 template <int K, int I, bool INSTR>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
-                          uint32_t complete, int rank_prev, Acc& acc) {
+                          uint32_t complete, int rank_prev, Acc& acc, const Split& sp,
+                          int c_lo = 0, int c_hi = INF) {
   const Level L = plan.lv[I];
   const int lane = lane_id();
   const int32_t B = L.bound >= 0 ? v[L.bound] : INF;
@@ -303,15 +333,32 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     }
   }
   blen = uni(blen);
+  if (!INSTR && sp.items && !use_src && c_lo == 0 && c_hi == INF && blen > sp.min_len) {
+    unsigned long long q = 0;
+    if (lane == 0) q = atomicAdd(sp.n_items, 1ull);
+    q = __shfl(q, 0, WAVE);
+    if ((long long)q < sp.cap) {
+      if (lane == 0) {
+        HeavyItem& it = sp.items[q];
+#pragma unroll
+        for (int j = 0; j < I; ++j) it.v[j] = v[j];
+        it.level = I;
+        it.r = sp.r;
+        it.base_len = blen;
+      }
+      return;
+    }
+  }
   slot = uni(slot);
   bstart = uni(bstart);
 
   int32_t* out = M.set[I - 2];
   uint32_t mine = complete & ~(1u << I);
-  if (blen <= CH) mine |= 1u << I;
+  const int c_end = min(blen, c_hi);
+  if (blen <= CH && c_lo == 0) mine |= 1u << I;
   int cum = 0;  // survivors of earlier chunks: rank of this chunk's first element
-  for (int c0 = 0; c0 < blen; c0 += CH) {
-    const int c1 = min(blen, c0 + CH);
+  for (int c0 = c_lo; c0 < c_end; c0 += CH) {
+    const int c1 = min(c_end, c0 + CH);
     int nout = 0;
     for (int r = c0; r < c1; r += WAVE) {
       const int idx = r + lane;
@@ -341,7 +388,7 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, cum + t, acc);
+        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
       }
     }
     cum += nout;
@@ -419,7 +466,8 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
           v[1] = uni(g.col[rs0 + i]);
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
-          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, i, acc);
+          const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)r};
+          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
         }
       }
       if constexpr (PER_ROOT) {
@@ -710,6 +758,60 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
   }
 }
 
+// Second phase: the bases of recorded prefixes of one loop depth LV, CH
+// elements per item; item t names a record through an exclusive prefix over
+// the records' piece counts.  Pieces do not share materialised sets, so the
+// loops below take their operands from the neighbour lists.  One launch per
+// depth keeps one chain of loops per kernel.
+template <int K, bool PER_ROOT, int LV>
+__global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const HeavyItem* items,
+                                                      const long long* piece_prefix,
+                                                      long long n_items,
+                                                      unsigned long long* queue, Out o) {
+  __shared__ WaveMem<K> mem[WPB];
+  WaveMem<K>& M = mem[threadIdx.x / WAVE];
+  const int lane = lane_id();
+  const long long total = piece_prefix[n_items];
+  const Split none{nullptr, nullptr, 0, INF, 0};
+  Acc acc{0ull, 0ull};
+  for (;;) {
+    long long t = 0;
+    if (lane == 0) t = (long long)atomicAdd(queue, 1ull);
+    t = __shfl(t, 0, WAVE);
+    if (t >= total) break;
+    long long lo = 0, hi = n_items + 1;
+    while (lo < hi) {
+      long long mid = (lo + hi) >> 1;
+      if (piece_prefix[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    const long long h = lo - 1;
+    const HeavyItem& it = items[h];
+    int32_t v[K], rs[K], rd[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      v[j] = (j < LV) ? uni(it.v[j]) : 0;
+      rs[j] = (j < LV) ? uni(g.rowptr[v[j]]) : 0;
+      rd[j] = (j < LV) ? uni(g.rowptr[v[j] + 1]) - rs[j] : 0;
+    }
+    const int c0 = (int)(t - piece_prefix[h]) * CH;
+    mat_level<K, LV, false>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
+    if constexpr (PER_ROOT) {
+      unsigned long long l, hh;
+      wave_sum_u128(acc.cnt, &l, &hh);
+      if (lane == 0 && (l | hh)) {
+        unsigned long long old = atomicAdd(o.per_root + it.r, l);
+        if (hh || old + l < old) atomicOr(o.acc + 5, 1ull);
+      }
+      acc.cnt = 0;
+    }
+  }
+  if constexpr (!PER_ROOT) {
+    unsigned long long l, hh;
+    wave_sum_u128(acc.cnt, &l, &hh);
+    if (lane == 0 && (l | hh)) add_u128(o.acc, l, hh);
+  }
+}
+
 // ------------------------------------------------------------------ census
 //
 // Motif census: one persistent launch over (graph, pattern, task) items of
@@ -776,7 +878,8 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
       v[1] = uni(g.col[rs0 + i]);
       rs[1] = uni(g.rowptr[v[1]]);
       rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
-      mat_level<K, 2, false>(g, plan, M, v, rs, rd, 0u, i, acc);
+      const Split none{nullptr, nullptr, 0, INF, 0};
+      mat_level<K, 2, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
     }
   }
 }
@@ -872,6 +975,164 @@ gz_status launch_by_k(int k, const dev::Graph& g, const Plan& plan,
       set_error("pattern size out of range");
       return GZ_EINVAL;
   }
+}
+
+template <int K, bool PR, int LV>
+gz_status launch_heavy_lv(const dev::Graph& g, const Plan& plan, const dev::HeavyItem* items,
+                          const long long* prefix, long long n_items, long long n_pieces,
+                          unsigned long long* queue, const dev::Out& o, hipStream_t st) {
+  if constexpr (LV < 2 || LV > K - 2) {
+    set_error("split depth outside the materialised loops");
+    return GZ_EINVAL;
+  } else {
+    auto kern = dev::k_mine_heavy<K, PR, LV>;
+    int per_cu = 0, devid = 0, cus = 0;
+    GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, dev::BLOCK, 0));
+    GZ_HIP(hipGetDevice(&devid));
+    GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+    long long blocks = (long long)std::max(per_cu, 1) * std::max(cus, 1);
+    blocks = std::max(1ll, std::min(blocks, (n_pieces + dev::WPB - 1) / dev::WPB));
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(dev::BLOCK), 0, st, g, plan, items,
+                       prefix, n_items, queue, o);
+    GZ_HIP(hipGetLastError());
+    return GZ_OK;
+  }
+}
+
+template <int K, bool PR>
+gz_status launch_heavy_k(int lv, const dev::Graph& g, const Plan& plan,
+                         const dev::HeavyItem* items, const long long* prefix, long long n_items,
+                         long long n_pieces, unsigned long long* queue, const dev::Out& o,
+                         hipStream_t st) {
+  switch (lv) {
+    case 2: return launch_heavy_lv<K, PR, 2>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 3: return launch_heavy_lv<K, PR, 3>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 4: return launch_heavy_lv<K, PR, 4>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 5: return launch_heavy_lv<K, PR, 5>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 6: return launch_heavy_lv<K, PR, 6>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    default:
+      set_error("split depth outside the materialised loops");
+      return GZ_EINVAL;
+  }
+}
+
+// Loop bases longer than this are split (GZ_SPLIT_MIN_LEN overrides).
+int split_min_len() {
+  const char* e = std::getenv("GZ_SPLIT_MIN_LEN");
+  if (e && *e) {
+    char* end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (end && *end == '\0' && v >= 0 && v <= INT32_MAX) return (int)v;
+  }
+  return 8 * dev::CH;
+}
+
+// Capacity of the record list (GZ_SPLIT_CAP overrides); prefixes met once
+// it is full are expanded in place by the first launch.
+long long split_cap() {
+  const char* e = std::getenv("GZ_SPLIT_CAP");
+  if (e && *e) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end && *end == '\0' && v >= 1 && v <= (1ll << 26)) return v;
+  }
+  return 1ll << 20;
+}
+
+// One launch per loop depth over the recorded prefixes of that depth.
+template <bool PR>
+gz_status launch_heavy(int k, int lv, const dev::Graph& g, const Plan& plan,
+                       const dev::HeavyItem* items, const long long* prefix, long long n_items,
+                       long long n_pieces, unsigned long long* queue, const dev::Out& o,
+                       hipStream_t st) {
+  switch (k) {
+    case 4: return launch_heavy_k<4, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 5: return launch_heavy_k<5, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 6: return launch_heavy_k<6, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 7: return launch_heavy_k<7, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 8: return launch_heavy_k<8, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    default:
+      set_error("split phase needs 4 <= k <= 8");
+      return GZ_EINVAL;
+  }
+}
+
+// Second phase of the generic path: read back the prefixes that phase one
+// recorded, group them by loop depth, and hand their bases out in pieces.
+gz_status run_heavy(const dev::Graph& dg, const Plan& plan, bool pr, dev::HeavyItem* d_heavy,
+                    long long cap, const unsigned long long* d_count, const dev::Out& o,
+                    hipStream_t st, void** scratch) {
+  unsigned long long n_rec = 0;
+  hipError_t e = hipMemcpyAsync(&n_rec, d_count, sizeof(n_rec), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  const long long n_items = std::min<long long>((long long)n_rec, cap);
+  if (e != hipSuccess) {
+    set_error(std::string("split list read-back: ") + hipGetErrorString(e));
+    return GZ_EDEVICE;
+  }
+  if (n_items <= 0) return GZ_OK;
+  std::vector<dev::HeavyItem> items((size_t)n_items);
+  e = hipMemcpy(items.data(), d_heavy, sizeof(dev::HeavyItem) * n_items, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    set_error(std::string("split list read-back: ") + hipGetErrorString(e));
+    return GZ_EDEVICE;
+  }
+  // counting sort by depth; per depth an exclusive prefix over piece counts
+  long long cnt[kMaxK + 1] = {0};
+  for (const auto& it : items) {
+    if (it.level < 2 || it.level > plan.k - 2) {
+      set_error("split list holds a record outside the materialised loops");
+      return GZ_EDEVICE;
+    }
+    ++cnt[it.level];
+  }
+  long long start[kMaxK + 2] = {0};
+  for (int lv = 0; lv <= kMaxK; ++lv) start[lv + 1] = start[lv] + cnt[lv];
+  std::vector<dev::HeavyItem> sorted((size_t)n_items);
+  {
+    long long fill[kMaxK + 1];
+    for (int lv = 0; lv <= kMaxK; ++lv) fill[lv] = start[lv];
+    for (const auto& it : items) sorted[(size_t)fill[it.level]++] = it;
+  }
+  // prefix of depth lv at offset start[lv] + lv (one extra entry per depth)
+  std::vector<long long> pre((size_t)n_items + kMaxK + 1, 0);
+  long long pieces[kMaxK + 1] = {0};
+  for (int lv = 2; lv <= plan.k - 2; ++lv) {
+    const long long off = start[lv] + lv;
+    pre[(size_t)off] = 0;
+    for (long long i = 0; i < cnt[lv]; ++i)
+      pre[(size_t)(off + i + 1)] =
+          pre[(size_t)(off + i)] + (sorted[(size_t)(start[lv] + i)].base_len + dev::CH - 1) / dev::CH;
+    pieces[lv] = pre[(size_t)(off + cnt[lv])];
+  }
+  char* buf = nullptr;
+  const size_t q_bytes = 256;
+  const size_t p_bytes = sizeof(long long) * pre.size();
+  if (hipMalloc(&buf, q_bytes + p_bytes) != hipSuccess) {
+    set_error("device allocation of the split prefix failed");
+    return GZ_ENOMEM;
+  }
+  *scratch = buf;
+  unsigned long long* queues = (unsigned long long*)buf;
+  long long* d_pre = (long long*)(buf + q_bytes);
+  if (hipMemcpy(d_heavy, sorted.data(), sizeof(dev::HeavyItem) * n_items,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_pre, pre.data(), p_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("split prefix upload failed");
+    return GZ_EDEVICE;
+  }
+  hipLaunchKernelGGL(dev::k_fill_u64, dim3(1), dim3(256), 0, st, queues, (long long)(kMaxK + 1));
+  for (int lv = 2; lv <= plan.k - 2; ++lv) {
+    if (!cnt[lv]) continue;
+    gz_status rc = pr ? launch_heavy<true>(plan.k, lv, dg, plan, d_heavy + start[lv],
+                                           d_pre + start[lv] + lv, cnt[lv], pieces[lv],
+                                           queues + lv, o, st)
+                      : launch_heavy<false>(plan.k, lv, dg, plan, d_heavy + start[lv],
+                                            d_pre + start[lv] + lv, cnt[lv], pieces[lv],
+                                            queues + lv, o, st);
+    if (rc) return rc;
+  }
+  return GZ_OK;
 }
 
 int chunk_for(int k) { return k <= 2 ? (1 << 30) : (k == 3 ? 64 : 16); }
@@ -1080,10 +1341,19 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   }
   // clique fast path: K_k (k >= 4) with chain bounds, rows of at most 16 words
   const bool use_clique = !instr && plan.k >= 4 && is_clique_chain(plan) && g->max_lo <= 1024;
-  if (clique_ops && (!use_clique || pr)) {
+  if (!rc && clique_ops && (!use_clique || pr)) {
     set_error("operation counts exist only for the clique path over all roots");
-    return GZ_ENOTSUP;
+    rc = GZ_ENOTSUP;
   }
+  // second phase of the generic path: long loop bases split into pieces
+  const bool split = !rc && !use_clique && !instr && plan.k >= 4;
+  const long long heavy_cap = split ? split_cap() : 0;
+  dev::HeavyItem* d_heavy = nullptr;
+  if (split && hipMalloc(&d_heavy, sizeof(dev::HeavyItem) * heavy_cap) != hipSuccess) {
+    set_error("device allocation of the split list failed");
+    rc = GZ_ENOMEM;
+  }
+  void* heavy_scratch = nullptr;
   CliqueLists own_lists;
   const CliqueLists* lists = nullptr;
   if (!rc && use_clique) {
@@ -1104,7 +1374,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
                        dim3(256), 0, st, d_acc, n_acc);
     dev::Graph dg{g->d_rowptr, g->d_col, g->d_lo, h.n};
-    dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1, 0};
+    dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
+                  split_min_len(), d_heavy, split ? heavy_cap : 0};
     dev::Out o{d_acc, d_acc + 8};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (kernel_ms) {
@@ -1125,6 +1396,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
       else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
       else rc = launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
     }
+    if (!rc && split && tasks.n_tasks > 0)
+      rc = run_heavy(dg, plan, pr, d_heavy, heavy_cap, d_acc + 6, o, st, &heavy_scratch);
     if (kernel_ms && !rc) {
       if (hipEventRecord(ev1, st) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess ||
           hipEventElapsedTime(kernel_ms, ev0, ev1) != hipSuccess) {
@@ -1146,6 +1419,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
   }
   (void)hipFree(d_acc);
+  if (d_heavy) (void)hipFree(d_heavy);
+  if (heavy_scratch) (void)hipFree(heavy_scratch);
   free_clique_lists(&own_lists);
   if (own_prefix) (void)hipFree(own_prefix);
   if (d_roots) (void)hipFree(d_roots);
