@@ -549,6 +549,37 @@ __device__ unsigned long long cl_count(const unsigned long long* rows, int W, in
   return total;
 }
 
+// 5-cliques of the root through the edge (C1[a], C1[b]), b < a, b in word
+// wb: the sum over c in m = row a AND row b of popcount(m AND row c).  The
+// first four words of m stay in registers, so each c costs one LDS read per
+// word in the common case instead of three.
+__device__ __forceinline__ unsigned long long k5_edge(const unsigned long long* rows, int W,
+                                                      int a, int b, int wb) {
+  const unsigned long long* ra = rows + (size_t)a * W;
+  const unsigned long long* rb = rows + (size_t)b * W;
+  const unsigned long long m0 = ra[0] & rb[0];
+  const unsigned long long m1 = wb >= 1 ? (ra[1] & rb[1]) : 0ull;
+  const unsigned long long m2 = wb >= 2 ? (ra[2] & rb[2]) : 0ull;
+  const unsigned long long m3 = wb >= 3 ? (ra[3] & rb[3]) : 0ull;
+  unsigned long long total = 0;
+  for (int wc = 0; wc <= wb; ++wc) {
+    unsigned long long mc = wc == 0 ? m0 : wc == 1 ? m1 : wc == 2 ? m2 : wc == 3 ? m3
+                                                                             : (ra[wc] & rb[wc]);
+    while (mc) {
+      const int c = wc * 64 + __builtin_ctzll(mc);
+      mc &= mc - 1;
+      const unsigned long long* rc = rows + (size_t)c * W;
+      unsigned int cnt = (unsigned)__popcll(m0 & rc[0]);
+      if (wc >= 1) cnt += (unsigned)__popcll(m1 & rc[1]);
+      if (wc >= 2) cnt += (unsigned)__popcll(m2 & rc[2]);
+      if (wc >= 3) cnt += (unsigned)__popcll(m3 & rc[3]);
+      for (int j = 4; j <= wc; ++j) cnt += (unsigned)__popcll(ra[j] & rb[j] & rc[j]);
+      total += cnt;
+    }
+  }
+  return total;
+}
+
 // K-cliques of the root that take C1[a] as their second vertex and a member
 // of word w of row a as their third
 template <int K, bool IN>
@@ -730,9 +761,87 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
     }
     __syncthreads();
     unsigned long long mine = 0;
-    for (int q = tid; q < d * Wd; q += CBLOCK) {
-      const int a = q / Wd, w = q - a * Wd;
-      if (w * 64 < a) mine += clique_unit<K, IN>(rows, W, a, w, ops);
+    if constexpr (K == 4) {
+      for (int q = tid; q < d * Wd; q += CBLOCK) {
+        const int a = q / Wd, w = q - a * Wd;
+        if (w * 64 < a) mine += clique_unit<K, IN>(rows, W, a, w, ops);
+      }
+    } else {
+      // Units are the edges (a, b), b < a, of the candidates' subgraph in
+      // row-major order, EG consecutive edges per unit, dealt round-robin:
+      // the deeper loops' cost varies far more between rows than between
+      // edges.  pref[a] becomes the exclusive prefix of the rows' edge counts.
+      int es = 0;
+      for (int j = 0; j < per; ++j) {
+        const int a = tid * per + j;
+        if (a < d) {
+          int c = 0;
+          for (int w = 0; w < Wd; ++w) c += __popcll(rows[a * W + w]);
+          pref[a] = c;
+          es += c;
+        }
+      }
+      int etot;
+      const int eexcl = wave_excl_scan(es, &etot);
+      __syncthreads();
+      if (lane == 0) s_tot[wv] = etot;
+      __syncthreads();
+      int ebase = 0, E = 0;
+      for (int w2 = 0; w2 < CWPB; ++w2) {
+        if (w2 < wv) ebase += s_tot[w2];
+        E += s_tot[w2];
+      }
+      int erun = ebase + eexcl;
+      for (int j = 0; j < per; ++j) {
+        const int a = tid * per + j;
+        if (a < d) {
+          const int c = pref[a];
+          pref[a] = erun;
+          erun += c;
+        }
+      }
+      __syncthreads();
+      constexpr int EG = 4;
+      for (int e0 = tid * EG; e0 < E; e0 += CBLOCK * EG) {
+        const int e1 = min(E, e0 + EG);
+        // the row holding edge e0: the last a with pref[a] <= e0 (non-empty)
+        int lo2 = 0, hi2 = d;
+        while (lo2 < hi2) {
+          const int mid = (lo2 + hi2) >> 1;
+          if (pref[mid] <= e0) lo2 = mid + 1; else hi2 = mid;
+        }
+        int a = lo2 - 1;
+        int r = e0 - pref[a];
+        int w = 0;
+        unsigned long long word = rows[a * W];
+        for (;;) {
+          const int c = __popcll(word);
+          if (r < c) break;
+          r -= c;
+          ++w;
+          word = rows[a * W + w];
+        }
+        for (; r > 0; --r) word &= word - 1;
+        for (int e = e0; e < e1; ++e) {
+          while (word == 0) {  // next word of row a (bits lie below a), else next row
+            if (++w * 64 >= a) {
+              ++a;
+              w = 0;
+            }
+            word = rows[a * W + w];
+          }
+          const int b = w * 64 + __builtin_ctzll(word);
+          word &= word - 1;
+          if constexpr (K == 5 && !IN) {
+            mine += k5_edge(rows, W, a, b, w);
+          } else {
+            int ids[8];
+            ids[0] = a;
+            ids[1] = b;
+            mine += cl_count<K - 4, IN>(rows, W, ids, 2, w + 1, ops);
+          }
+        }
+      }
     }
     if constexpr (PER_ROOT) {
       unsigned long long l, h;

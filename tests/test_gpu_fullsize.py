@@ -5,6 +5,8 @@ oracle's own normalisation and reindex entry by entry, and properties that hold
 at any size (per-root counts summing to the total) are checked on the GPU.
 The GPU runs the same kernels and launch configuration as the benchmark."""
 
+import json
+import os
 import sys
 
 import numpy as np
@@ -93,6 +95,52 @@ def test_rmat20_cliques(rmat20, k):
     _say(f"rmat20 k{k} total {total}")
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "fullsize_roots.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("fullsize_roots.json not generated")
+    with open(GOLDEN) as f:
+        return json.load(f)["graphs"]
+
+
+def _tiny_roots(O, seed, n, max_vol=500):
+    """Seeded roots of degree >= 2 whose neighbours' degrees sum to at most
+    max_vol: cheap enough for the oracle under any schedule of the
+    workloads' patterns."""
+    deg = np.diff(O.rowptr).astype(np.int64)
+    cs = np.concatenate([[0], np.cumsum(deg[O.col])])
+    rp = O.rowptr.astype(np.int64)
+    vol = cs[rp[1:]] - cs[rp[:-1]]
+    pool = np.nonzero((deg >= 2) & (vol <= max_vol))[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(pool, min(n, pool.size), replace=False)).astype(np.int32)
+
+
+def _golden_parity(G, gname, nm, adj):
+    """Analytic schedule: per-root counts at the stored roots (drawn across
+    four strata of two-hop volume) against the oracle's stored counts."""
+    entry = _golden()[gname][nm]
+    s = gz.compile_pattern(adj, True)
+    assert list(s.info()["order"]) == entry["order"], (gname, nm)
+    roots = np.array(entry["roots"], np.int32)
+    want = np.array([int(c) for c in entry["counts"]], np.uint64)
+    _say(gname, nm, "analytic: gpu on", roots.size, "stored roots")
+    got = gz.count_roots(G, s, roots)
+    assert np.array_equal(got, want), (gname, nm)
+    return s
+
+
+def _learned_parity(G, O, gname, nm, adj, s_an, seed):
+    learn.install()
+    sl = gz.compile_pattern_graph(G, np.array(adj, np.uint8), True, gz.SCHED_LEARNED)
+    if sl.info()["order"] != s_an.info()["order"]:
+        roots = _tiny_roots(O, seed, 6)
+        _per_root_parity(G, O, adj, True, sl, roots, f"{gname} {nm} learned")
+
+
 @pytest.fixture(scope="module")
 def rmat22():
     return _load("rmat22")
@@ -101,21 +149,13 @@ def rmat22():
 @pytest.mark.parametrize("nm", ["c4", "diamond", "tailed_triangle", "house", "k5e"])
 def test_rmat22_induced_patterns(rmat22, nm):
     """The vertex-induced 4-cycle, diamond, tailed triangle, house and K5-e on
-    R-MAT scale 22: per-root parity on sampled roots for the analytic and the
-    learned schedule."""
+    R-MAT scale 22: the analytic schedule's per-root counts at stored roots
+    of every degree stratum, and the learned schedule's against the oracle
+    run here at low-volume roots."""
     G, O = rmat22
     adj = P.named(nm)
-    # the house's hub-heavy schedules make mid-degree roots costly for the
-    # oracle: uniform roots only
-    n_mid = 0 if nm == "house" else 20
-    n_uni = 100 if nm == "house" else 300
-    roots = _sample_roots(O, 220 + len(nm), n_uni, n_mid, mid_rank=(5000, 200000))
-    s = gz.compile_pattern(adj, True)
-    _per_root_parity(G, O, adj, True, s, roots, f"rmat22 {nm} analytic")
-    learn.install()
-    sl = gz.compile_pattern_graph(G, np.array(adj, np.uint8), True, gz.SCHED_LEARNED)
-    if sl.info()["order"] != s.info()["order"]:
-        _per_root_parity(G, O, adj, True, sl, roots, f"rmat22 {nm} learned")
+    s = _golden_parity(G, "rmat22", nm, adj)
+    _learned_parity(G, O, "rmat22", nm, adj, s, 220 + len(nm))
 
 
 @pytest.fixture(scope="module")
@@ -130,13 +170,9 @@ def learned_graphs():
 @pytest.mark.parametrize("nm", ["c6chord03", "c6chord02", "k6e", "k7e"])
 def test_learned_schedule_graphs(learned_graphs, gname, nm):
     """Held-out 6/7-vertex patterns on the learned-schedule workloads: the
-    learned and the analytic schedule both agree with the oracle per root."""
+    analytic schedule at stored roots of every stratum, the learned one
+    against the oracle at low-volume roots."""
     G, O = learned_graphs[gname]
-    adj = learn.held_out_patterns()[nm]
-    roots = _sample_roots(O, 500 + len(nm), 60, 0)
-    learn.install()
-    s_an = gz.compile_pattern(adj, True)
-    s_le = gz.compile_pattern_graph(G, adj, True, gz.SCHED_LEARNED)
-    _per_root_parity(G, O, adj.tolist(), True, s_an, roots, f"{gname} {nm} analytic")
-    if s_le.info()["order"] != s_an.info()["order"]:
-        _per_root_parity(G, O, adj.tolist(), True, s_le, roots, f"{gname} {nm} learned")
+    adj = P.named(nm)
+    s = _golden_parity(G, gname, nm, adj)
+    _learned_parity(G, O, gname, nm, adj, s, 500 + len(nm))
