@@ -177,7 +177,11 @@ void gz_free_schedule(gz_schedule* s);
  * the first launch and expanded in 256-element pieces by a second; the host
  * reads the record count in between.  The record list holds 2^20 prefixes
  * (GZ_SPLIT_CAP, 1..2^26, overrides it); prefixes met after it fills are
- * expanded in place.  Invalid override values are ignored.  Errors: GZ_EINVAL (NULL handle),
+ * expanded in place.  Invalid override values are ignored.
+ * The last loop of a vertex-induced pattern may count an item by
+ * inclusion-exclusion over its negative lists instead of walking its
+ * shortest positive list; GZ_IE_FORCE=1 makes every item with negative
+ * lists take that evaluation (a test switch: the count is the same).  Errors: GZ_EINVAL (NULL handle),
  * GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified), GZ_ENOMEM,
  * GZ_EDEVICE.
  */

@@ -54,6 +54,7 @@ struct Plan {
   int32_t k;
   int32_t induced;
   Level lv[kMaxK];
+  int32_t ie_force = 0;  // last loop: inclusion-exclusion for every item (tests)
 };
 
 // ---------------------------------------------------------------- patterns

@@ -34,6 +34,8 @@
 namespace gz {
 namespace dev {
 
+// last-loop items with a shorter walk never try inclusion-exclusion
+constexpr int IE_MIN = 256;
 constexpr int WAVE = 64;
 constexpr int CH = 256;               // base elements per materialised chunk
 constexpr int BLOCK = 256;
@@ -82,6 +84,7 @@ struct WaveMem {
   int32_t it_srclen[WAVE];
   int32_t it_urs[WAVE];
   int32_t it_urd[WAVE];
+  int32_t it_ie[WAVE];
 };
 
 struct Acc {
@@ -151,7 +154,23 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
 
 // ------------------------------------------------------------ last loop
 
-template <int K, bool INSTR>
+// Count of the last loop for the items of one chunk of loop K-2.
+//
+// Each item's candidates are x < B in every positive list (the loop's
+// pattern neighbours, or the materialised `src` set plus the rest) and in no
+// negative list (pattern non-neighbours, vertex-induced mode), x distinct
+// from the `excl` vertices.  Two evaluations give the same number:
+//  * direct: walk the shortest bounded positive list and probe the others;
+//  * inclusion-exclusion over the negative lists N_1..N_m:
+//      sum over T of (-1)^|T| |(all positive lists) and (N_j, j in T)|,
+//    each term walked from its own shortest bounded list, less the excl
+//    vertices that pass every test.  An item takes it when the sum of its
+//    terms' walk lengths is below the direct one: a hub's long positive list
+//    is then never walked when its negative lists are short.
+// Every (item, term, element) pair is one lane's work; an item's terms are
+// all counted within this call, so the signed partial sums of the call
+// total the (non-negative) count of its items.
+template <int K, bool INSTR, bool IE>
 __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                            const int32_t (&v)[K], const int32_t (&rs)[K],
                            const int32_t (&rd)[K], uint32_t complete,
@@ -167,6 +186,8 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
   const int32_t Bu = (L.bound >= 0 && !item_bound) ? v[L.bound] : INF;
   const int32_t* srcset = M.set[src_idx];
   const int src_full = use_src ? M.set_len[src_idx] : 0;
+  const int n_pos = __popc(pos) + (use_src ? 1 : 0);
+  const int m_neg = __popc(neg);
 
   // bounded lengths of the rows of loops j < J (exact when the bound does
   // not depend on the item; otherwise the full row, an upper bound that is
@@ -179,6 +200,7 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
       ulen[j] = item_bound ? rd[j] : bounded_len(g, v[j], rs[j], rd[j], Bu, L.bound == j);
   }
 
+  long long local = 0;  // signed: inclusion-exclusion terms subtract
   for (int g0 = 0; g0 < n_items; g0 += WAVE) {
     const int t = g0 + lane;
     const bool valid = t < n_items;
@@ -187,6 +209,10 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     const int32_t urd = valid ? g.rowptr[u + 1] - urs : 0;
     const int32_t B = item_bound ? u : Bu;
     int slot = SRC_SLOT, blen = INF, bstart = 0, slen = 0;
+    int len[K];  // bounded length of each list of the loop (j <= J)
+#pragma unroll
+    for (int j = 0; j < K; ++j) len[j] = 0;
+    bool ie = false;
     if (valid) {
       if (use_src) {
         slen = (L.src == J && item_bound) ? t : lower_bound(srcset, src_full, B);
@@ -195,23 +221,23 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         if ((pos >> j) & 1u) {
-          int len = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
-          if (len < blen) {
-            blen = len;
+          len[j] = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
+          if (len[j] < blen) {
+            blen = len[j];
             slot = j;
             bstart = rs[j];
           }
         }
       }
       if ((pos >> J) & 1u) {
-        int len = bounded_len(g, u, urs, urd, B, item_bound);
-        if (len < blen) {
-          blen = len;
+        len[J] = bounded_len(g, u, urs, urd, B, item_bound);
+        if (len[J] < blen) {
+          blen = len[J];
           slot = J;
           bstart = urs;
         }
       }
-      if (INSTR) {
+      if constexpr (INSTR) {
         // extension of the enclosing set: its elements below u (the item's
         // rank) plus the added lists; otherwise every list of the loop
         const bool ext = (L.acct & 0x80u) != 0;
@@ -223,55 +249,132 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
             b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
         if ((all >> J) & 1u) b += 4ull * (unsigned)bounded_len(g, u, urs, urd, B, item_bound) + 8ull;
         acc.bytes += b;
+      } else if (IE && m_neg > 0 && (plan.ie_force || blen > IE_MIN)) {
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if ((neg >> j) & 1u)
+            len[j] = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
+        if ((neg >> J) & 1u) len[J] = bounded_len(g, u, urs, urd, B, item_bound);
+        // walk length of the inclusion-exclusion terms
+        long long cost = n_pos > 1 ? blen : 0;
+        for (uint32_t T = 1; T < (1u << m_neg); ++T) {
+          int mn = blen;
+          uint32_t rest = neg;
+          for (int q = 0; q < m_neg; ++q) {
+            const int j = __ffs(rest) - 1;
+            rest &= rest - 1;
+            if ((T >> q) & 1u) mn = min(mn, len[j]);
+          }
+          cost += mn;
+        }
+        ie = plan.ie_force || 2 * cost < (long long)blen;
       }
     } else {
       blen = 0;
     }
-    int total;
-    const int pref = wave_excl_scan(blen, &total);
+    const bool any_ie = IE && __ballot(ie) != 0ull;
+    const uint32_t n_terms = any_ie ? (1u << m_neg) : 1u;
     M.it_u[lane] = u;
-    M.it_pref[lane] = pref;
-    M.it_bstart[lane] = bstart;
-    M.it_slot[lane] = slot;
     M.it_srclen[lane] = slen;
     M.it_urs[lane] = urs;
     M.it_urd[lane] = urd;
-    wave_sync();
-    const int nvalid = min(WAVE, n_items - g0);
-    for (int p0 = 0; p0 < total; p0 += WAVE) {
-      const int p = p0 + lane;
-      bool ok = p < total;
-      if (ok) {
-        // item of pair p: the last i with pref[i] <= p
-        int lo = 0, hi = nvalid;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (M.it_pref[mid] <= p) lo = mid + 1; else hi = mid;
+    M.it_ie[lane] = ie ? 1 : 0;
+    for (uint32_t T = 0; T < n_terms; ++T) {
+      // the term's lists: the positive ones and the negative ones picked by T
+      uint32_t tmask = 0;
+      {
+        uint32_t rest = neg;
+        for (int q = 0; q < m_neg; ++q) {
+          const int j = __ffs(rest) - 1;
+          rest &= rest - 1;
+          if ((T >> q) & 1u) tmask |= 1u << j;
         }
-        const int i = lo - 1;
-        const int e = p - M.it_pref[i];
-        const int sl = M.it_slot[i];
-        const int32_t x = (sl == SRC_SLOT) ? srcset[e] : g.col[M.it_bstart[i] + e];
-        const int32_t uu = M.it_u[i];
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-          if ((L.excl >> j) & 1u) ok = ok && (x != v[j]);
-        if ((L.excl >> J) & 1u) ok = ok && (x != uu);
-        if (ok && use_src && sl != SRC_SLOT) ok = contains(srcset, M.it_srclen[i], x);
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-          if (ok && ((pos >> j) & 1u) && sl != j) ok = contains(g.col + rs[j], ulen[j], x);
-        if (ok && ((pos >> J) & 1u) && sl != J)
-          ok = contains(g.col + M.it_urs[i], M.it_urd[i], x);
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-          if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], ulen[j], x);
-        if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + M.it_urs[i], M.it_urd[i], x);
       }
-      acc.cnt += ok ? 1ull : 0ull;
+      int elen = 0, eslot = slot, estart = bstart;
+      if (!ie) {
+        elen = (T == 0) ? blen : 0;
+      } else if (T == 0) {
+        if (n_pos == 1) local += blen;  // a single bounded list: its length
+        else elen = blen;
+      } else {
+        elen = blen;
+        for (int j = 0; j <= J; ++j) {
+          if (((tmask >> j) & 1u) && len[j] < elen) {
+            elen = len[j];
+            eslot = j;
+            estart = (j == J) ? urs : rs[j];
+          }
+        }
+      }
+      int total;
+      const int pref = wave_excl_scan(elen, &total);
+      M.it_pref[lane] = pref;
+      M.it_bstart[lane] = estart;
+      M.it_slot[lane] = eslot;
+      wave_sync();
+      const int nvalid = min(WAVE, n_items - g0);
+      const long long sign = (__popc(T) & 1) ? -1ll : 1ll;
+      for (int p0 = 0; p0 < total; p0 += WAVE) {
+        const int p = p0 + lane;
+        bool ok = p < total;
+        if (ok) {
+          // item of pair p: the last i with pref[i] <= p
+          int lo = 0, hi = nvalid;
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (M.it_pref[mid] <= p) lo = mid + 1; else hi = mid;
+          }
+          const int i = lo - 1;
+          const int e = p - M.it_pref[i];
+          const int sl = M.it_slot[i];
+          const int32_t x = (sl == SRC_SLOT) ? srcset[e] : g.col[M.it_bstart[i] + e];
+          const int32_t uu = M.it_u[i];
+          const bool direct = M.it_ie[i] == 0;
+          if (direct) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+              if ((L.excl >> j) & 1u) ok = ok && (x != v[j]);
+            if ((L.excl >> J) & 1u) ok = ok && (x != uu);
+          }
+          if (ok && use_src && sl != SRC_SLOT) ok = contains(srcset, M.it_srclen[i], x);
+#pragma unroll
+          for (int j = 0; j < J; ++j)
+            if (ok && (((pos | tmask) >> j) & 1u) && sl != j)
+              ok = contains(g.col + rs[j], ulen[j], x);
+          if (ok && (((pos | tmask) >> J) & 1u) && sl != J)
+            ok = contains(g.col + M.it_urs[i], M.it_urd[i], x);
+          if (direct) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+              if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], ulen[j], x);
+            if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + M.it_urs[i], M.it_urd[i], x);
+          }
+        }
+        local += ok ? sign : 0ll;
+      }
+      wave_sync();
     }
-    wave_sync();
+    if (ie) {
+      // inclusion-exclusion counted the excl vertices that pass every test
+      for (int j = 0; j <= J; ++j) {
+        if (!((L.excl >> j) & 1u)) continue;
+        const int32_t y = (j == J) ? u : v[j];
+        bool ok = y < B;
+        if (ok && use_src) ok = contains(srcset, slen, y);
+        for (int jj = 0; jj < J; ++jj)
+          if (ok && ((pos >> jj) & 1u)) ok = contains(g.col + rs[jj], ulen[jj], y);
+        if (ok && ((pos >> J) & 1u)) ok = contains(g.col + urs, urd, y);
+        for (int jj = 0; jj < J; ++jj)
+          if (ok && ((neg >> jj) & 1u)) ok = !contains(g.col + rs[jj], ulen[jj], y);
+        if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + urs, urd, y);
+        local -= ok ? 1ll : 0ll;
+      }
+    }
   }
+  // the call's items are complete: their signed partial sums total >= 0
+#pragma unroll
+  for (int d = WAVE / 2; d >= 1; d >>= 1) local += __shfl_xor(local, d, WAVE);
+  if (lane == 0) acc.cnt += (unsigned long long)local;
 }
 
 // ---------------------------------------------------- materialised loops
@@ -294,7 +397,7 @@ struct Split {
   int32_t r;                     // current root slot
 };
 
-template <int K, int I, bool INSTR>
+template <int K, int I, bool INSTR, bool IE>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
                           uint32_t complete, int rank_prev, Acc& acc, const Split& sp,
@@ -382,13 +485,13 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     if (lane == 0) M.set_len[I - 2] = nout;
     wave_sync();
     if constexpr (I == K - 2) {
-      last_level<K, INSTR>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
+      last_level<K, INSTR, IE>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
     } else {
       for (int t = 0; t < nout; ++t) {
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
+        mat_level<K, I + 1, INSTR, IE>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
       }
     }
     cum += nout;
@@ -423,7 +526,7 @@ __device__ __forceinline__ void wave_sum_u128(unsigned long long x,
   *hi = h;
 }
 
-template <int K, bool PER_ROOT, bool INSTR>
+template <int K, bool PER_ROOT, bool INSTR, bool IE>
 __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out o) {
   __shared__ WaveMem<K> mem[WPB];
   WaveMem<K>& M = mem[threadIdx.x / WAVE];
@@ -459,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
       if constexpr (K == 2) {
         if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
       } else if constexpr (K == 3) {
-        last_level<K, INSTR>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
+        last_level<K, INSTR, IE>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
                              end - begin, begin, acc);
       } else {
         for (int32_t i = begin; i < end; ++i) {
@@ -467,7 +570,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
           const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)r};
-          mat_level<K, 2, INSTR>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
+          mat_level<K, 2, INSTR, IE>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
         }
       }
       if constexpr (PER_ROOT) {
@@ -872,7 +975,7 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
 // the records' piece counts.  Pieces do not share materialised sets, so the
 // loops below take their operands from the neighbour lists.  One launch per
 // depth keeps one chain of loops per kernel.
-template <int K, bool PER_ROOT, int LV>
+template <int K, bool PER_ROOT, int LV, bool IE>
 __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const HeavyItem* items,
                                                       const long long* piece_prefix,
                                                       long long n_items,
@@ -903,7 +1006,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const 
       rd[j] = (j < LV) ? uni(g.rowptr[v[j] + 1]) - rs[j] : 0;
     }
     const int c0 = (int)(t - piece_prefix[h]) * CH;
-    mat_level<K, LV, false>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
+    mat_level<K, LV, false, IE>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
     if constexpr (PER_ROOT) {
       unsigned long long l, hh;
       wave_sum_u128(acc.cnt, &l, &hh);
@@ -981,14 +1084,14 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
   if constexpr (K == 2) {
     if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
   } else if constexpr (K == 3) {
-    last_level<K, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin, begin, acc);
+    last_level<K, false, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin, begin, acc);
   } else {
     for (int32_t i = begin; i < end; ++i) {
       v[1] = uni(g.col[rs0 + i]);
       rs[1] = uni(g.rowptr[v[1]]);
       rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
       const Split none{nullptr, nullptr, 0, INF, 0};
-      mat_level<K, 2, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
+      mat_level<K, 2, false, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
     }
   }
 }
@@ -1050,10 +1153,10 @@ namespace {
     }                                                                     \
   } while (0)
 
-template <int K, bool PR, bool IN>
+template <int K, bool PR, bool IN, bool IE>
 gz_status launch_k(const dev::Graph& g, const Plan& plan, const dev::Tasks& T,
                    const dev::Out& o, hipStream_t st) {
-  auto kern = dev::k_mine<K, PR, IN>;
+  auto kern = dev::k_mine<K, PR, IN, IE>;
   int per_cu = 0;
   GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, dev::BLOCK, 0));
   int devid = 0;
@@ -1069,17 +1172,17 @@ gz_status launch_k(const dev::Graph& g, const Plan& plan, const dev::Tasks& T,
   return GZ_OK;
 }
 
-template <bool PR, bool IN>
+template <bool PR, bool IN, bool IE = false>
 gz_status launch_by_k(int k, const dev::Graph& g, const Plan& plan,
                       const dev::Tasks& T, const dev::Out& o, hipStream_t st) {
   switch (k) {
-    case 2: return launch_k<2, PR, IN>(g, plan, T, o, st);
-    case 3: return launch_k<3, PR, IN>(g, plan, T, o, st);
-    case 4: return launch_k<4, PR, IN>(g, plan, T, o, st);
-    case 5: return launch_k<5, PR, IN>(g, plan, T, o, st);
-    case 6: return launch_k<6, PR, IN>(g, plan, T, o, st);
-    case 7: return launch_k<7, PR, IN>(g, plan, T, o, st);
-    case 8: return launch_k<8, PR, IN>(g, plan, T, o, st);
+    case 2: return launch_k<2, PR, IN, IE>(g, plan, T, o, st);
+    case 3: return launch_k<3, PR, IN, IE>(g, plan, T, o, st);
+    case 4: return launch_k<4, PR, IN, IE>(g, plan, T, o, st);
+    case 5: return launch_k<5, PR, IN, IE>(g, plan, T, o, st);
+    case 6: return launch_k<6, PR, IN, IE>(g, plan, T, o, st);
+    case 7: return launch_k<7, PR, IN, IE>(g, plan, T, o, st);
+    case 8: return launch_k<8, PR, IN, IE>(g, plan, T, o, st);
     default:
       set_error("pattern size out of range");
       return GZ_EINVAL;
@@ -1089,12 +1192,13 @@ gz_status launch_by_k(int k, const dev::Graph& g, const Plan& plan,
 template <int K, bool PR, int LV>
 gz_status launch_heavy_lv(const dev::Graph& g, const Plan& plan, const dev::HeavyItem* items,
                           const long long* prefix, long long n_items, long long n_pieces,
-                          unsigned long long* queue, const dev::Out& o, hipStream_t st) {
+                          unsigned long long* queue, const dev::Out& o, hipStream_t st,
+                          bool ie) {
   if constexpr (LV < 2 || LV > K - 2) {
     set_error("split depth outside the materialised loops");
     return GZ_EINVAL;
   } else {
-    auto kern = dev::k_mine_heavy<K, PR, LV>;
+    auto kern = ie ? dev::k_mine_heavy<K, PR, LV, true> : dev::k_mine_heavy<K, PR, LV, false>;
     int per_cu = 0, devid = 0, cus = 0;
     GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, dev::BLOCK, 0));
     GZ_HIP(hipGetDevice(&devid));
@@ -1112,17 +1216,23 @@ template <int K, bool PR>
 gz_status launch_heavy_k(int lv, const dev::Graph& g, const Plan& plan,
                          const dev::HeavyItem* items, const long long* prefix, long long n_items,
                          long long n_pieces, unsigned long long* queue, const dev::Out& o,
-                         hipStream_t st) {
+                         hipStream_t st, bool ie) {
   switch (lv) {
-    case 2: return launch_heavy_lv<K, PR, 2>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 3: return launch_heavy_lv<K, PR, 3>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 4: return launch_heavy_lv<K, PR, 4>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 5: return launch_heavy_lv<K, PR, 5>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 6: return launch_heavy_lv<K, PR, 6>(g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 2: return launch_heavy_lv<K, PR, 2>(g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 3: return launch_heavy_lv<K, PR, 3>(g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 4: return launch_heavy_lv<K, PR, 4>(g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 5: return launch_heavy_lv<K, PR, 5>(g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 6: return launch_heavy_lv<K, PR, 6>(g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
     default:
       set_error("split depth outside the materialised loops");
       return GZ_EINVAL;
   }
+}
+
+// An environment variable set to "1".
+bool env_flag(const char* name) {
+  const char* e = std::getenv(name);
+  return e && e[0] == '1' && e[1] == '\0';
 }
 
 // Loop bases longer than this are split (GZ_SPLIT_MIN_LEN overrides).
@@ -1153,13 +1263,13 @@ template <bool PR>
 gz_status launch_heavy(int k, int lv, const dev::Graph& g, const Plan& plan,
                        const dev::HeavyItem* items, const long long* prefix, long long n_items,
                        long long n_pieces, unsigned long long* queue, const dev::Out& o,
-                       hipStream_t st) {
+                       hipStream_t st, bool ie) {
   switch (k) {
-    case 4: return launch_heavy_k<4, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 5: return launch_heavy_k<5, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 6: return launch_heavy_k<6, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 7: return launch_heavy_k<7, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
-    case 8: return launch_heavy_k<8, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st);
+    case 4: return launch_heavy_k<4, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 5: return launch_heavy_k<5, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 6: return launch_heavy_k<6, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 7: return launch_heavy_k<7, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
+    case 8: return launch_heavy_k<8, PR>(lv, g, plan, items, prefix, n_items, n_pieces, queue, o, st, ie);
     default:
       set_error("split phase needs 4 <= k <= 8");
       return GZ_EINVAL;
@@ -1170,7 +1280,7 @@ gz_status launch_heavy(int k, int lv, const dev::Graph& g, const Plan& plan,
 // recorded, group them by loop depth, and hand their bases out in pieces.
 gz_status run_heavy(const dev::Graph& dg, const Plan& plan, bool pr, dev::HeavyItem* d_heavy,
                     long long cap, const unsigned long long* d_count, const dev::Out& o,
-                    hipStream_t st, void** scratch) {
+                    hipStream_t st, void** scratch, bool ie) {
   unsigned long long n_rec = 0;
   hipError_t e = hipMemcpyAsync(&n_rec, d_count, sizeof(n_rec), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1235,10 +1345,10 @@ gz_status run_heavy(const dev::Graph& dg, const Plan& plan, bool pr, dev::HeavyI
     if (!cnt[lv]) continue;
     gz_status rc = pr ? launch_heavy<true>(plan.k, lv, dg, plan, d_heavy + start[lv],
                                            d_pre + start[lv] + lv, cnt[lv], pieces[lv],
-                                           queues + lv, o, st)
+                                           queues + lv, o, st, ie)
                       : launch_heavy<false>(plan.k, lv, dg, plan, d_heavy + start[lv],
                                             d_pre + start[lv] + lv, cnt[lv], pieces[lv],
-                                            queues + lv, o, st);
+                                            queues + lv, o, st, ie);
     if (rc) return rc;
   }
   return GZ_OK;
@@ -1409,7 +1519,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     const int32_t* roots, int64_t n_roots, uint64_t* per_root,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
                     float* kernel_ms, bool clique_ops) {
-  const Plan& plan = s->plan;
+  Plan plan = s->plan;
+  plan.ie_force = env_flag("GZ_IE_FORCE");
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
   const int chunk = chunk_for(plan.k);
@@ -1454,6 +1565,11 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     set_error("operation counts exist only for the clique path over all roots");
     rc = GZ_ENOTSUP;
   }
+  // inclusion-exclusion in the last loop: only where it has negative lists
+  // and no restriction bound, the case where its positive list can be a
+  // whole hub row (its kernels hold more registers)
+  const bool ie = !instr && plan.k >= 3 && plan.lv[plan.k - 1].sub != 0 &&
+                  (plan.lv[plan.k - 1].bound < 0 || plan.ie_force);
   // second phase of the generic path: long loop bases split into pieces
   const bool split = !rc && !use_clique && !instr && plan.k >= 4;
   const long long heavy_cap = split ? split_cap() : 0;
@@ -1501,12 +1617,14 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                 : (clique_ops ? launch_clique<false, true>(plan.k, dg, *lists, o, st)
                               : launch_clique<false, false>(plan.k, dg, *lists, o, st));
       } else if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
-      else if (pr) rc = launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
+      else if (pr) rc = ie ? launch_by_k<true, false, true>(plan.k, dg, plan, dt, o, st)
+                           : launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
       else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
-      else rc = launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
+      else rc = ie ? launch_by_k<false, false, true>(plan.k, dg, plan, dt, o, st)
+                   : launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
     }
     if (!rc && split && tasks.n_tasks > 0)
-      rc = run_heavy(dg, plan, pr, d_heavy, heavy_cap, d_acc + 6, o, st, &heavy_scratch);
+      rc = run_heavy(dg, plan, pr, d_heavy, heavy_cap, d_acc + 6, o, st, &heavy_scratch, ie);
     if (kernel_ms && !rc) {
       if (hipEventRecord(ev1, st) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess ||
           hipEventElapsedTime(kernel_ms, ev0, ev1) != hipSuccess) {

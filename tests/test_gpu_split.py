@@ -1,9 +1,16 @@
-"""GPU parity of the two-phase generic path: prefixes whose loop base is long
-are recorded by the first launch and expanded in pieces by a second.  The
-threshold and the record-list capacity are forced low so that almost every
-prefix takes the second phase, or the list overflows and the rest are
-expanded in place; counts must stay bit-exact against the oracle, in total
-and per root.  A two-hub graph exercises the default threshold."""
+"""GPU parity of the generic path's alternative evaluations.
+
+Two-phase split: prefixes whose loop base is long are recorded by the first
+launch and expanded in pieces by a second.  The threshold and the
+record-list capacity are forced low so that almost every prefix takes the
+second phase, or the list overflows and the rest are expanded in place; a
+two-hub graph exercises the default threshold.
+
+Inclusion-exclusion in the last loop: forced for every item that has
+negative lists (GZ_IE_FORCE=1), on every pattern of up to 5 vertices and on
+larger ones; the two-hub graph takes it by itself for hub-rooted tails.
+
+Counts must stay bit-exact against the oracle, in total and per root."""
 
 import os
 import sys
@@ -25,8 +32,8 @@ def gpu():
         pytest.skip("no GPU")
     gz.library()
     yield
-    os.environ.pop("GZ_SPLIT_MIN_LEN", None)
-    os.environ.pop("GZ_SPLIT_CAP", None)
+    for k in ("GZ_SPLIT_MIN_LEN", "GZ_SPLIT_CAP", "GZ_IE_FORCE"):
+        os.environ.pop(k, None)
 
 
 def _say(*a):
@@ -120,6 +127,57 @@ def test_two_hubs_default_threshold(hub_case, nm):
         # the same count with splitting switched off (threshold above any base)
         with _env(GZ_SPLIT_MIN_LEN=1 << 30):
             assert gz.count(G, s) == want, (nm, induced)
+
+
+def test_forced_inclusion_exclusion_small_patterns():
+    graphs = [synth.er_edges(14, 0.45, 61), synth.rmat_edges(6, 6, seed=62),
+              synth.chung_lu_edges(40, 2.3, 6.0, 63, cap=False), synth.star_edges(9)]
+    for e in graphs:
+        G = gz.load_edges(*e)
+        O = oracle.from_edge_tuple(e)
+        for k in (3, 4, 5):
+            for pat in P.connected_patterns(k):
+                want = oracle.count(O, pat, True)
+                s = gz.compile_pattern(pat, True)
+                with _env(GZ_IE_FORCE=1):
+                    assert gz.count(G, s) == want, (k, pat)
+
+
+def test_forced_inclusion_exclusion_medium(cl_case):
+    G, want = cl_case
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        with _env(GZ_IE_FORCE=1):
+            _say("ie", nm, induced)
+            assert gz.count(G, s) == want[(nm, induced)], (nm, induced)
+        with _env(GZ_IE_FORCE=1, GZ_SPLIT_MIN_LEN=0):
+            assert gz.count(G, s) == want[(nm, induced)], (nm, induced, "split")
+
+
+@pytest.mark.parametrize("nm", ["house", "tailed_triangle", "c6chord02"])
+def test_forced_inclusion_exclusion_per_root(nm):
+    e = synth.rmat_edges(9, 8, seed=64)
+    G = gz.load_edges(*e)
+    O = oracle.from_edge_tuple(e)
+    pat = P.named(nm)
+    s = gz.compile_pattern(pat, True)
+    roots = np.arange(O.n, dtype=np.int32)
+    _, want = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                           roots=roots, per_root=True)
+    with _env(GZ_IE_FORCE=1):
+        got = gz.count_roots(G, s, roots)
+    assert np.array_equal(got, want)
+
+
+def test_larger_patterns_forced_inclusion_exclusion():
+    e = synth.er_edges(13, 0.6, 65)
+    G = gz.load_edges(*e)
+    O = oracle.from_edge_tuple(e)
+    for nm in ("c6", "c6chord03", "k6e", "c7", "k7e", "p6", "c8"):
+        pat = P.named(nm)
+        want = oracle.count(O, pat, True)
+        with _env(GZ_IE_FORCE=1):
+            assert gz.count(G, gz.compile_pattern(pat, True)) == want, nm
 
 
 def test_invalid_overrides_ignored():
