@@ -127,6 +127,12 @@ struct CliqueLists {
   int32_t* heavy_r = nullptr;
   int64_t n_heavy = 0;
   int32_t heavy_max_lo = 0;
+  // heavy roots (sorted by candidate count, largest first) fall into
+  // contiguous size classes: roots [bucket_begin[b], bucket_begin[b + 1])
+  // have rows of at most bucket_w[b] 64-bit words
+  int32_t n_buckets = 0;
+  int32_t bucket_w[4] = {0, 0, 0, 0};
+  int64_t bucket_begin[5] = {0, 0, 0, 0, 0};
 };
 
 void set_error(const std::string& msg);

@@ -65,8 +65,12 @@ struct Tasks {
   long long heavy_cap;
 };
 
-// acc[0..1]: 128-bit count; acc[2..3]: 128-bit bytes; acc[4]: queue head;
-// acc[5]: per-root overflow flag
+// acc[0..1]: 128-bit count; acc[2..3]: 128-bit bytes (or operations);
+// acc[4]: queue head; acc[5]: per-root overflow flag; acc[6]: split record
+// count; acc[8..11]: queue heads of the clique workgroup launches; per-root
+// counts start at acc[ACC_HEAD]
+constexpr int ACC_BLOCK_QUEUES = 8;
+constexpr int ACC_HEAD = 16;
 struct Out {
   unsigned long long* acc;
   unsigned long long* per_root;
@@ -703,13 +707,15 @@ __device__ __forceinline__ unsigned long long clique_unit(const unsigned long lo
 
 // Probe plan of row p: slot 0 probes C1[0..p) into N+(C1[p]) (binary search
 // in global memory); slot 1 scans N+(C1[p]) and probes each element into
-// C1[0..p) (binary search in LDS) - cheaper unless N+(C1[p]) is much longer.
+// C1[0..p) (binary search in LDS, most misses rejected by a filter first) -
+// the scan is taken unless N+(C1[p]) is more than twice as long (the
+// threshold measured fastest on R-MAT scale 20 among 1, 2, 4 and 16).
 __device__ __forceinline__ void row_plan(const Graph& g, int32_t x, int p, int32_t* urs,
                                          int32_t* ulen, int32_t* slot, int* len) {
   const int32_t lx = g.lo[x];
   *urs = g.rowptr[x];
   *ulen = lx;
-  const bool scan = lx <= 4 * p;
+  const bool scan = lx <= 2 * p;
   *slot = scan ? 1 : 0;
   *len = scan ? lx : p;
 }
@@ -791,9 +797,19 @@ __global__ __launch_bounds__(BLOCK) void k_clique_wave(Graph g, RootList L, Out 
 
 // Workgroup path: roots with more than 64 candidates (at most 64 W).
 // Dynamic LDS: rows[S*W] (64-bit) then xs, pref, urs, ulen, slot (S int32
-// each), S = 64 W.
+// each), S = 64 W, then a FILT_BITS-bit membership filter of C1: most
+// scanned neighbours are not in C1 and are rejected by one filter read
+// instead of a binary search.
+constexpr int FILT_BITS = 1 << 15;
+constexpr int FILT_WORDS = FILT_BITS / 32;
+
+__device__ __forceinline__ uint32_t filt_hash(int32_t y) {
+  return ((uint32_t)y * 0x9E3779B1u) >> 17;  // 15 bits, multiplicative
+}
+
 template <int K, bool PER_ROOT, bool IN>
-__global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Out o, int W) {
+__global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Out o, int W,
+                                                         unsigned long long* queue) {
   extern __shared__ unsigned long long dyn[];
   __shared__ int s_task;
   __shared__ int s_tot[CWPB];
@@ -804,12 +820,13 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
   int32_t* urs = pref + S;
   int32_t* ulen = urs + S;
   int32_t* slot = ulen + S;
+  uint32_t* filt = (uint32_t*)(slot + S);
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / WAVE;
   unsigned long long cnt = 0, ops = 0;
   for (;;) {
-    if (tid == 0) s_task = (int)atomicAdd(o.acc + 7, 1ull);
+    if (tid == 0) s_task = (int)atomicAdd(queue, 1ull);
     __syncthreads();
     const long long t = s_task;
     __syncthreads();
@@ -819,6 +836,8 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
     const int32_t rs0 = g.rowptr[v0];
     const int Wd = (d + 63) / 64;
     for (int q = tid; q < d * Wd; q += CBLOCK) rows[(q / Wd) * W + (q % Wd)] = 0ull;
+    for (int q = tid; q < FILT_WORDS; q += CBLOCK) filt[q] = 0u;
+    __syncthreads();
     // probe lengths of the rows and their exclusive prefix over the block
     const int per = (d + CBLOCK - 1) / CBLOCK;
     int mysum = 0;
@@ -827,6 +846,8 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
       if (a < d) {
         const int32_t x = g.col[rs0 + a];
         xs[a] = x;
+        const uint32_t hx = filt_hash(x);
+        atomicOr(&filt[hx >> 5], 1u << (hx & 31));
         int len;
         row_plan(g, x, a, &urs[a], &ulen[a], &slot[a], &len);
         pref[a] = len;
@@ -859,7 +880,18 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
         if (pref[mid] <= p) lo2 = mid + 1; else hi2 = mid;
       }
       const int a = lo2 - 1;
-      const int bit = row_probe(g, xs, a, p - pref[a], slot[a], urs[a], ulen[a]);
+      const int e = p - pref[a];
+      int bit = -1;
+      if (slot[a] == 0) {
+        bit = contains(g.col + urs[a], ulen[a], xs[e]) ? e : -1;
+      } else {
+        const int32_t y = g.col[urs[a] + e];
+        const uint32_t hy = filt_hash(y);
+        if ((filt[hy >> 5] >> (hy & 31)) & 1u) {
+          const int q = lower_bound(xs, a, y);
+          bit = (q < a && xs[q] == y) ? q : -1;
+        }
+      }
       if (bit >= 0) atomicOr(&rows[a * W + (bit >> 6)], 1ull << (bit & 63));
     }
     __syncthreads();
@@ -1393,10 +1425,49 @@ gz_status build_clique_lists(const HostGraph& h, const int32_t* roots, int64_t n
                      return a.first > b.first;
                    });
   std::vector<int32_t> hvv, hvr;
-  for (auto& x : hv) {
+  // size classes of 2, 4 and 8 words, then the rest: smaller rows take less
+  // LDS, so more workgroups share a CU
+  const int32_t classes[3] = {2, 4, 8};
+  out->n_buckets = 0;
+  for (size_t i = 0; i < hv.size(); ++i) {
+    const auto& x = hv[i];
     hvv.push_back(roots ? roots[x.second] : x.second);
     hvr.push_back(x.second);
     out->heavy_max_lo = std::max(out->heavy_max_lo, x.first);
+  }
+  {
+    // walk from the smallest roots (the end) up, closing a class when the
+    // next root needs more words
+    const int64_t nh = (int64_t)hv.size();
+    int32_t ws[4];
+    int64_t ends[4];
+    int nb = 0;
+    int64_t i = nh;
+    for (int c = 0; c < 3 && i > 0; ++c) {
+      int64_t j = i;
+      while (j > 0 && (hv[(size_t)(j - 1)].first + 63) / 64 <= classes[c]) --j;
+      if (j < i) {
+        ws[nb] = classes[c];
+        ends[nb] = i;
+        ++nb;
+        i = j;
+      }
+    }
+    if (i > 0) {
+      ws[nb] = (hv[0].first + 63) / 64;
+      ends[nb] = i;
+      ++nb;
+    }
+    // classes from the largest rows (front of the list) to the smallest
+    int64_t begin = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int src = nb - 1 - b;
+      out->bucket_w[b] = ws[src];
+      out->bucket_begin[b] = begin;
+      begin = ends[src];
+    }
+    out->bucket_begin[nb] = begin;
+    out->n_buckets = nb;
   }
   gz_status rc = upload_i32(lv, &out->light_v, st);
   if (!rc) rc = upload_i32(lr, &out->light_r, st);
@@ -1417,12 +1488,35 @@ void free_clique_lists(CliqueLists* c) {
   *c = CliqueLists();
 }
 
+// Side streams of the current device (default priority, created once, kept
+// for the process): the clique size classes run on them concurrently.
+hipStream_t side_stream(int i) {
+  static std::mutex mu;
+  static hipStream_t streams[16][4] = {};
+  int dev_id = 0;
+  if (hipGetDevice(&dev_id) != hipSuccess || dev_id < 0 || dev_id >= 16 || i < 0 || i >= 4)
+    return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev_id][i] &&
+      hipStreamCreateWithFlags(&streams[dev_id][i], hipStreamNonBlocking) != hipSuccess)
+    streams[dev_id][i] = nullptr;
+  return streams[dev_id][i];
+}
+
 template <int K, bool PR, bool IN>
 gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::Out& o,
                           hipStream_t st) {
   int devid = 0, cus = 0, per_cu = 0;
   GZ_HIP(hipGetDevice(&devid));
   GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  // the size classes below start with the wave path, not after it
+  hipEvent_t fork = nullptr;
+  if (C.n_buckets > 0 && (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+                          hipEventRecord(fork, st) != hipSuccess)) {
+    if (fork) (void)hipEventDestroy(fork);
+    set_error("clique fork event failed");
+    return GZ_EDEVICE;
+  }
   if (C.n_light > 0) {
     const int batch = 8;
     auto kw = dev::k_clique_wave<K, PR, IN>;
@@ -1432,26 +1526,62 @@ gz_status launch_clique_k(const dev::Graph& g, const CliqueLists& C, const dev::
     blocks = std::max(1ll, std::min(blocks, need));
     dev::RootList L{C.light_v, C.light_r, C.n_light};
     hipLaunchKernelGGL(kw, dim3((unsigned)blocks), dim3(dev::BLOCK), 0, st, g, L, o, batch);
-    GZ_HIP(hipGetLastError());
-  }
-  if (C.n_heavy > 0) {
-    auto kb = dev::k_clique_block<K, PR, IN>;
-    const int W = (C.heavy_max_lo + 63) / 64;
-    const size_t S = 64 * (size_t)W;
-    const size_t lds = S * W * sizeof(unsigned long long) + 5 * S * sizeof(int32_t);
-    GZ_HIP(hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb, dev::CBLOCK, lds));
-    if (per_cu < 1) {
-      set_error("clique workgroup path does not fit in LDS");
+    if (hipGetLastError() != hipSuccess) {
+      if (fork) (void)hipEventDestroy(fork);
+      set_error("clique wave launch failed");
       return GZ_EDEVICE;
     }
-    long long blocks = std::min<long long>((long long)per_cu * std::max(cus, 1), C.n_heavy);
-    dev::RootList L{C.heavy_v, C.heavy_r, C.n_heavy};
-    hipLaunchKernelGGL(kb, dim3((unsigned)blocks), dim3(dev::CBLOCK), lds, st, g, L, o, W);
-    GZ_HIP(hipGetLastError());
   }
-  return GZ_OK;
+  // one launch per size class, each with its own queue, on side streams so
+  // that the classes share the CUs instead of each draining alone
+  if (C.n_buckets <= 0) return GZ_OK;
+  hipStream_t side[4];
+  hipEvent_t join[4] = {nullptr, nullptr, nullptr, nullptr};
+  gz_status rc = GZ_OK;
+  for (int b = 0; b < C.n_buckets && !rc; ++b) {
+    side[b] = side_stream(b);
+    if (!side[b]) {
+      set_error("side stream creation failed");
+      rc = GZ_EDEVICE;
+    }
+  }
+  for (int b = 0; b < C.n_buckets && !rc; ++b) {
+    const long long n_b = C.bucket_begin[b + 1] - C.bucket_begin[b];
+    auto kb = dev::k_clique_block<K, PR, IN>;
+    const int W = C.bucket_w[b];
+    const size_t S = 64 * (size_t)W;
+    const size_t lds = S * W * sizeof(unsigned long long) + 5 * S * sizeof(int32_t) +
+                       dev::FILT_WORDS * sizeof(uint32_t);
+    if (hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb, dev::CBLOCK, lds) !=
+            hipSuccess ||
+        per_cu < 1) {
+      set_error("clique workgroup path does not fit in LDS");
+      rc = GZ_EDEVICE;
+      break;
+    }
+    if (hipStreamWaitEvent(side[b], fork, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&join[b], hipEventDisableTiming) != hipSuccess) {
+      set_error("clique stream fork failed");
+      rc = GZ_EDEVICE;
+      break;
+    }
+    long long blocks = std::min<long long>((long long)per_cu * std::max(cus, 1), n_b);
+    dev::RootList L{C.heavy_v + C.bucket_begin[b], C.heavy_r + C.bucket_begin[b], n_b};
+    hipLaunchKernelGGL(kb, dim3((unsigned)std::max(blocks, 1ll)), dim3(dev::CBLOCK), lds, side[b],
+                       g, L, o, W, o.acc + dev::ACC_BLOCK_QUEUES + b);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(join[b], side[b]) != hipSuccess ||
+        hipStreamWaitEvent(st, join[b], 0) != hipSuccess) {
+      set_error("clique workgroup launch failed");
+      rc = GZ_EDEVICE;
+      break;
+    }
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  for (hipEvent_t e : join)
+    if (e) (void)hipEventDestroy(e);
+  return rc;
 }
 
 template <bool PR, bool IN>
@@ -1553,7 +1683,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   }
 
   unsigned long long* d_acc = nullptr;
-  const long long n_acc = 8 + (pr ? nr : 0);
+  const long long n_acc = dev::ACC_HEAD + (pr ? nr : 0);
   gz_status rc = GZ_OK;
   if (hipMalloc(&d_acc, sizeof(unsigned long long) * n_acc) != hipSuccess) {
     set_error("device allocation of the accumulators failed");
@@ -1601,7 +1731,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     dev::Graph dg{g->d_rowptr, g->d_col, g->d_lo, h.n};
     dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
                   split_min_len(), d_heavy, split ? heavy_cap : 0};
-    dev::Out o{d_acc, d_acc + 8};
+    dev::Out o{d_acc, d_acc + dev::ACC_HEAD};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (kernel_ms) {
       *kernel_ms = 0.0f;
@@ -1670,7 +1800,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
       set_error("a per-root count does not fit in 64 bits");
       return GZ_EOVERFLOW;
     }
-    for (int64_t i = 0; i < nr; ++i) per_root[i] = hacc[8 + i];
+    for (int64_t i = 0; i < nr; ++i) per_root[i] = hacc[dev::ACC_HEAD + i];
   }
   return GZ_OK;
 }
