@@ -99,6 +99,40 @@ def cpu_baseline(edges, pattern_names, induced, orders, bounds, target_s):
     return nbytes / dt / 1e9, desc, dt
 
 
+def learned_vs_analytic(reps=2):
+    """Kernel time of the learned and the analytic schedule choice for the
+    held-out patterns (6-cycle with chord {0,3} or {0,2}, K6-e, K7-e) on two
+    graphs outside the model's corpus whose full counts finish in seconds:
+    R-MAT scale 10 (edge factor 16, seed 8801) and Chung-Lu n = 4000
+    (exponent 2.3, mean degree 10, seed 8802).  Best of `reps` timed runs per
+    schedule; the counts must agree."""
+    import numpy as np
+    from paper_1911_12877_amd import gz, learn, synth
+    if not os.path.exists(learn.MODEL_PATH):
+        return None
+    learn.install()
+    cases = []
+    ta = tl = 0.0
+    same = True
+    for gname, e in (("rmat10", synth.rmat_edges(10, 16, seed=8801)),
+                     ("cl4000", synth.chung_lu_edges(4000, 2.3, 10.0, 8802, cap=True))):
+        G = gz.load_edges(*e)
+        for nm, a in learn.held_out_patterns().items():
+            sa = gz.compile_pattern(a, True)
+            sl = gz.compile_pattern_graph(G, a, True, gz.SCHED_LEARNED)
+            ca, ma = learn.time_schedule(G, sa, reps=reps)
+            cl, ml = learn.time_schedule(G, sl, reps=reps)
+            same = same and ca == cl
+            ta += ma
+            tl += ml
+            cases.append({"graph": gname, "pattern": nm, "analytic_ms": round(ma, 3),
+                          "learned_ms": round(ml, 3)})
+            log(f"learned vs analytic {gname} {nm}: {ma:.2f} ms -> {ml:.2f} ms")
+    return {"analytic_ms": round(ta, 3), "learned_ms": round(tl, 3),
+            "speedup": round(ta / tl, 3) if tl > 0 else None, "counts_equal": same,
+            "cases": cases}
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 5 copies of 1 GiB (2^28 int32)
     device to device; each moves 1 GiB in and 1 GiB out of HBM."""
@@ -122,6 +156,8 @@ def main():
     ap.add_argument("--workload", default="rmat20-cliques", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned vs analytic schedule comparison")
     ap.add_argument("--no-alg-bytes", action="store_true",
                     help="skip the instrumented pass (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -230,6 +266,8 @@ def main():
         cpu = {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": desc, "seconds": round(dt, 2)}
 
+    lva = None if args.no_learned else learned_vs_analytic()
+
     out = {
         "metric": METRIC, "value": round(value, 2) if have_bytes else None, "unit": "GB/s",
         "n_gpus": 1,
@@ -247,6 +285,7 @@ def main():
         "prep_s": round(t_prep, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_vs_analytic": lva,
     }
     print(json.dumps(out), flush=True)
 
