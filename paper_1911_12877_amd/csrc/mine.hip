@@ -672,16 +672,35 @@ __device__ __forceinline__ unsigned long long k5_edge(const unsigned long long* 
   for (int wc = 0; wc <= wb; ++wc) {
     unsigned long long mc = wc == 0 ? m0 : wc == 1 ? m1 : wc == 2 ? m2 : wc == 3 ? m3
                                                                              : (ra[wc] & rb[wc]);
+    // two members c per iteration: their row loads are independent
     while (mc) {
-      const int c = wc * 64 + __builtin_ctzll(mc);
+      const int c1 = wc * 64 + __builtin_ctzll(mc);
       mc &= mc - 1;
-      const unsigned long long* rc = rows + (size_t)c * W;
-      unsigned int cnt = (unsigned)__popcll(m0 & rc[0]);
-      if (wc >= 1) cnt += (unsigned)__popcll(m1 & rc[1]);
-      if (wc >= 2) cnt += (unsigned)__popcll(m2 & rc[2]);
-      if (wc >= 3) cnt += (unsigned)__popcll(m3 & rc[3]);
-      for (int j = 4; j <= wc; ++j) cnt += (unsigned)__popcll(ra[j] & rb[j] & rc[j]);
-      total += cnt;
+      const bool two = mc != 0ull;
+      const int c2 = two ? wc * 64 + __builtin_ctzll(mc) : c1;
+      if (two) mc &= mc - 1;
+      const unsigned long long* r1 = rows + (size_t)c1 * W;
+      const unsigned long long* r2 = rows + (size_t)c2 * W;
+      unsigned int n1 = (unsigned)__popcll(m0 & r1[0]);
+      unsigned int n2 = (unsigned)__popcll(m0 & r2[0]);
+      if (wc >= 1) {
+        n1 += (unsigned)__popcll(m1 & r1[1]);
+        n2 += (unsigned)__popcll(m1 & r2[1]);
+      }
+      if (wc >= 2) {
+        n1 += (unsigned)__popcll(m2 & r1[2]);
+        n2 += (unsigned)__popcll(m2 & r2[2]);
+      }
+      if (wc >= 3) {
+        n1 += (unsigned)__popcll(m3 & r1[3]);
+        n2 += (unsigned)__popcll(m3 & r2[3]);
+      }
+      for (int j = 4; j <= wc; ++j) {
+        const unsigned long long m = ra[j] & rb[j];
+        n1 += (unsigned)__popcll(m & r1[j]);
+        n2 += (unsigned)__popcll(m & r2[j]);
+      }
+      total += n1 + (two ? n2 : 0u);
     }
   }
   return total;
@@ -903,7 +922,8 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
       }
     } else {
       // Units are the edges (a, b), b < a, of the candidates' subgraph in
-      // row-major order, EG consecutive edges per unit, dealt round-robin:
+      // row-major order, dealt round-robin (EG consecutive edges per unit; 1
+      // measured fastest of 1, 2, 4, 8 for K5 on R-MAT scale 20):
       // the deeper loops' cost varies far more between rows than between
       // edges.  pref[a] becomes the exclusive prefix of the rows' edge counts.
       int es = 0;
@@ -936,7 +956,7 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
         }
       }
       __syncthreads();
-      constexpr int EG = 4;
+      constexpr int EG = 1;
       for (int e0 = tid * EG; e0 < E; e0 += CBLOCK * EG) {
         const int e1 = min(E, e0 + EG);
         // the row holding edge e0: the last a with pref[a] <= e0 (non-empty)
