@@ -256,8 +256,9 @@ gz_status gz_census_create(const gz_graph* const* graphs, int32_t n_graphs,
 gz_status gz_census_run(gz_census* c, uint64_t* counts, float* ms);
 
 /* Autotune the launch: task granularity (first-loop candidates per item) of
- * 3-vertex patterns and of larger ones, and items per queue pop.  Each
- * candidate is rebuilt, captured and replayed twice; the fastest is kept.
+ * 3-vertex patterns (8, 32, 128) and of larger ones (1, 4, 16), and items per
+ * queue pop (1, 4); defaults before tuning are (128, 1, 1).  Each candidate is
+ * rebuilt, captured and replayed twice; the fastest is kept.
  * params[3] receives (granularity k=3, granularity k>=4, items per pop),
  * best_ms its replay time.  Either may be NULL. */
 gz_status gz_census_tune(gz_census* c, int32_t* params, float* best_ms);

@@ -1842,7 +1842,8 @@ struct gz_census_impl {
   unsigned long long* d_counts = nullptr;
   int n_pairs = 0;
   long long n_tasks = 0;
-  int chunk3 = 64, chunk45 = 16, batch = 1;
+  // defaults: the tuner's pick on the smallest graphs of the 64-graph batch
+  int chunk3 = 128, chunk45 = 1, batch = 1;
   int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -2010,8 +2011,8 @@ gz_status census_run(void* p, uint64_t* counts, float* ms) {
 // twice, the fastest kept.
 gz_status census_tune(void* p, int32_t* params, float* best_ms) {
   auto* c = (gz_census_impl*)p;
-  const int c3s[] = {32, 128};
-  const int c45s[] = {4, 16, 64};
+  const int c3s[] = {8, 32, 128};
+  const int c45s[] = {1, 4, 16};
   const int batches[] = {1, 4};
   float best = -1.0f;
   int b3 = c->chunk3, b45 = c->chunk45, bb = c->batch;

@@ -84,7 +84,7 @@ def test_census_tune_keeps_counts(census_case):
     c = gz.Census(G, S)
     before, _ = c.run()
     params, best = c.tune()
-    assert params[0] in (32, 128) and params[1] in (4, 16, 64) and params[2] in (1, 4)
+    assert params[0] in (8, 32, 128) and params[1] in (1, 4, 16) and params[2] in (1, 4)
     after, _ = c.run()
     assert np.array_equal(before, after)
 
