@@ -656,6 +656,44 @@ __device__ unsigned long long cl_count(const unsigned long long* rows, int W, in
   return total;
 }
 
+// Position of the r-th (0-based) set bit of x, which has more than r set
+// bits: halving by popcount, six steps.
+__device__ __forceinline__ int select64(unsigned long long x, int r) {
+  int pos = 0;
+  int c = __popc((unsigned int)x);
+  if (r >= c) {
+    r -= c;
+    x >>= 32;
+    pos = 32;
+  }
+  c = __popc((unsigned int)x & 0xFFFFu);
+  if (r >= c) {
+    r -= c;
+    x >>= 16;
+    pos += 16;
+  }
+  c = __popc((unsigned int)x & 0xFFu);
+  if (r >= c) {
+    r -= c;
+    x >>= 8;
+    pos += 8;
+  }
+  c = __popc((unsigned int)x & 0xFu);
+  if (r >= c) {
+    r -= c;
+    x >>= 4;
+    pos += 4;
+  }
+  c = __popc((unsigned int)x & 0x3u);
+  if (r >= c) {
+    r -= c;
+    x >>= 2;
+    pos += 2;
+  }
+  if (r >= (int)(x & 1u)) pos += 1;
+  return pos;
+}
+
 // 5-cliques of the root through the edge (C1[a], C1[b]), b < a, b in word
 // wb: the sum over c in m = row a AND row b of popcount(m AND row c).  The
 // first four words of m stay in registers, so each c costs one LDS read per
@@ -976,7 +1014,7 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
           ++w;
           word = rows[a * W + w];
         }
-        for (; r > 0; --r) word &= word - 1;
+        word &= ~0ull << select64(word, r);  // drop the r lowest members
         for (int e = e0; e < e1; ++e) {
           while (word == 0) {  // next word of row a (bits lie below a), else next row
             if (++w * 64 >= a) {
