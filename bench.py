@@ -188,6 +188,12 @@ def main():
     t0 = time.perf_counter()
     G = gz.load_edges(*edges, stream=stream)
     t_prep = time.perf_counter() - t0
+    # the same preparation on the device (radix sorts); identical arrays
+    t0 = time.perf_counter()
+    Gd = gz.load_edges(*edges, flags=gz.GRAPH_PREP_DEVICE, stream=stream)
+    t_prep_dev = time.perf_counter() - t0
+    assert Gd.info() == G.info()
+    del Gd
     info = G.info()
     log(f"prepared graph n={info['n']} nnz={info['nnz']} max_deg={info['max_deg']} "
         f"max_lo={info['max_lo_deg']} in {t_prep:.2f}s")
@@ -283,6 +289,7 @@ def main():
         "alg_bytes": {nm: b for nm, b in zip(wl["patterns"], alg_bytes)},
         "counts_per_s": round(sum(counts) / (ms_per_step / 1e3), 1),
         "prep_s": round(t_prep, 3),
+        "prep_device_s": round(t_prep_dev, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned_vs_analytic": lva,

@@ -57,6 +57,9 @@ typedef struct gz_schedule gz_schedule;
 #define GZ_GRAPH_NO_REINDEX  2u  /* keep the caller's ids (orientation off);
                                     counts are unchanged, only speed differs  */
 #define GZ_GRAPH_DEVICE_PTRS 4u  /* the input arrays are device pointers      */
+#define GZ_GRAPH_PREP_DEVICE 8u  /* gz_load_edges only: normalise and reindex
+                                    on the device (radix sorts); the result is
+                                    identical to the host preparation         */
 
 /*
  * Load a graph given as CSR: rowptr[n+1] (rowptr[0] = 0, non-decreasing,
@@ -76,7 +79,12 @@ gz_status gz_load_graph(const int32_t* rowptr, const int32_t* colidx,
 /*
  * Load a graph given as a raw edge list src[m], dst[m] over n vertices.  The
  * list may hold self-loops, duplicates and one or both orientations of an
- * edge; it is always normalised (GZ_GRAPH_NORMALIZE is implied).
+ * edge; it is always normalised (GZ_GRAPH_NORMALIZE is implied).  With
+ * GZ_GRAPH_PREP_DEVICE the normalisation and the degree reindex run on the
+ * current device (m <= 2^31) and the prepared graph is copied back to the
+ * handle's host copy; the arrays are the same as those of the host path.
+ * Errors: GZ_EINVAL (n < 0, m < 0, an endpoint outside [0, n), a result of
+ * 2^31 or more entries, unknown flags), GZ_ENOMEM, GZ_EDEVICE.
  */
 gz_status gz_load_edges(const int32_t* src, const int32_t* dst, int64_t m,
                         int32_t n, uint32_t flags, void* hip_stream,

@@ -17,7 +17,8 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libgz.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["graph_prep.cpp", "compiler.cpp", "capi.cpp", "learned.cpp", "mine.hip", "mlp.hip"]
+SOURCES = ["graph_prep.cpp", "compiler.cpp", "capi.cpp", "learned.cpp", "mine.hip", "mlp.hip",
+           "prep.hip"]
 
 # gfx950 only; packed FP32 instructions are switched off for every HIP
 # translation unit (the library uses no floating point on the device, the

@@ -14,6 +14,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
                     float* kernel_ms, bool clique_ops = false);
 void free_graph_tasks(gz_graph* g);
+gz_status device_prepare_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                               bool device_inputs, bool reindex, hipStream_t st, gz_graph* g);
 
 gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
                         const gz_schedule* const* scheds, int32_t n_scheds, void** out);
@@ -83,9 +85,8 @@ gz_status host_copy(const int32_t* p, size_t count, bool device, hipStream_t st,
   return GZ_OK;
 }
 
-gz_status finish_graph(gz_graph* g, uint32_t flags, hipStream_t st, gz_graph** out) {
-  if (!(flags & GZ_GRAPH_NO_REINDEX)) graph_reindex(&g->host);
-  graph_finish(&g->host);
+// Degree statistics of a prepared graph (cost-model features).
+void graph_stats(gz_graph* g) {
   const HostGraph& h = g->host;
   double sd = 0, sd2 = 0, sl = 0, sl2 = 0;
   for (int32_t v = 0; v < h.n; ++v) {
@@ -106,6 +107,12 @@ gz_status finish_graph(gz_graph* g, uint32_t flags, hipStream_t st, gz_graph** o
   g->stats[5] = sl / n;
   g->stats[6] = sl > 0 ? sl2 / sl : 0;
   g->stats[7] = g->max_lo;
+}
+
+gz_status finish_graph(gz_graph* g, uint32_t flags, hipStream_t st, gz_graph** out) {
+  if (!(flags & GZ_GRAPH_NO_REINDEX)) graph_reindex(&g->host);
+  graph_finish(&g->host);
+  graph_stats(g);
   gz_status rc = upload_graph(g, st);
   if (rc) {
     release_graph(g);
@@ -257,7 +264,8 @@ gz_status gz_load_edges(const int32_t* src, const int32_t* dst, int64_t m, int32
     set_error("NULL argument");
     return GZ_EINVAL;
   }
-  if (flags & ~(uint32_t)(GZ_GRAPH_NORMALIZE | GZ_GRAPH_NO_REINDEX | GZ_GRAPH_DEVICE_PTRS)) {
+  if (flags & ~(uint32_t)(GZ_GRAPH_NORMALIZE | GZ_GRAPH_NO_REINDEX | GZ_GRAPH_DEVICE_PTRS |
+                          GZ_GRAPH_PREP_DEVICE)) {
     set_error("unknown graph flags");
     return GZ_EINVAL;
   }
@@ -267,6 +275,21 @@ gz_status gz_load_edges(const int32_t* src, const int32_t* dst, int64_t m, int32
   }
   hipStream_t st = (hipStream_t)hip_stream;
   const bool dev = flags & GZ_GRAPH_DEVICE_PTRS;
+  if (flags & GZ_GRAPH_PREP_DEVICE) {
+    auto* g = new (std::nothrow) gz_graph();
+    if (!g) {
+      set_error("out of host memory");
+      return GZ_ENOMEM;
+    }
+    gz_status rc = device_prepare_edges(src, dst, m, n, dev, !(flags & GZ_GRAPH_NO_REINDEX), st, g);
+    if (rc) {
+      release_graph(g);
+      return rc;
+    }
+    graph_stats(g);
+    *out = g;
+    return GZ_OK;
+  }
   std::vector<int32_t> hs, hd;
   const int32_t *s = nullptr, *d = nullptr;
   gz_status rc = host_copy(src, (size_t)m, dev, st, &hs, &s);

@@ -27,6 +27,7 @@ GZ_OK, GZ_EINVAL, GZ_ENOMEM, GZ_EDEVICE, GZ_EOVERFLOW, GZ_ENOTSUP = 0, -1, -2, -
 GRAPH_NORMALIZE = 1
 GRAPH_NO_REINDEX = 2
 GRAPH_DEVICE_PTRS = 4
+GRAPH_PREP_DEVICE = 8
 SCHED_ANALYTIC = 0
 SCHED_LEARNED = 1
 SCHED_NO_RESTRICT = 8
