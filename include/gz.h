@@ -243,14 +243,17 @@ gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream
 /* ------------------------------------------------------------ motif census */
 
 /*
- * Batched counting of many patterns (k <= 5) over many graphs in one
- * persistent launch: every (graph, pattern, first-loop task) item is handed
- * out from one queue, and each (graph, pattern) pair keeps its own 128-bit
- * count.  The zeroing of the accumulators and the launch are captured once
- * into a HIP graph and replayed by gz_census_run.  Graph and schedule
+ * Batched counting of many patterns (k <= 7) over many graphs in one
+ * persistent launch per size class (patterns of 2-5 vertices; of 6-7):
+ * every (graph, pattern, first-loop task) item of a class is handed out from
+ * one queue, and each (graph, pattern) pair keeps its own 128-bit count.
+ * The zeroing of the accumulators and the launches are captured once into a
+ * HIP graph and replayed by gz_census_run.  Graph and schedule
  * handles must outlive the census object; counts follow the order
  * counts[graph * n_scheds + sched].  The census runs on its own stream and
- * each call returns when its work is done.
+ * each call returns when its work is done.  Errors: GZ_EINVAL (NULL or empty
+ * inputs, a graph on another device), GZ_ENOTSUP (a pattern of 8 vertices),
+ * GZ_ENOMEM, GZ_EDEVICE.
  */
 typedef struct gz_census gz_census;
 

@@ -1129,25 +1129,37 @@ struct CensusPair {
   int32_t plan;           // index into the plan table
   int32_t chunk;
   int32_t bounded1;
+  int32_t out;            // (graph, pattern) slot of the 128-bit accumulators
 };
 
 struct CensusArgs {
   const Graph* graphs;
   const Plan* plans;
-  const CensusPair* pairs;
+  const CensusPair* pairs;       // the pairs of one size class
   const long long* pair_prefix;  // n_pairs + 1
   int n_pairs;
   int batch;
-  unsigned long long* counts;    // 2 per pair, then the queue head
+  unsigned long long* counts;    // 2 per (graph, pattern) slot
+  unsigned long long* queue;     // this class's queue head
 };
 
 // one wave's LDS, whatever pattern size its current task has (waves of a
-// workgroup may run tasks of different sizes at the same time)
-union CensusWaveMem {
+// workgroup may run tasks of different sizes at the same time).  Patterns
+// of 2-5 and of 6-7 vertices run in two kernels of the same captured graph,
+// so the small ones do not pay the large ones' registers.
+template <int KMAX>
+union CensusWaveMem;
+template <>
+union CensusWaveMem<5> {
   WaveMem<2> m2;
   WaveMem<3> m3;
   WaveMem<4> m4;
   WaveMem<5> m5;
+};
+template <>
+union CensusWaveMem<7> {
+  WaveMem<6> m6;
+  WaveMem<7> m7;
 };
 
 template <int K>
@@ -1186,11 +1198,12 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
   }
 }
 
+template <int KMAX>
 __global__ __launch_bounds__(BLOCK) void k_census(CensusArgs A) {
-  __shared__ CensusWaveMem mem[WPB];
-  CensusWaveMem& M = mem[threadIdx.x / WAVE];
+  __shared__ CensusWaveMem<KMAX> mem[WPB];
+  CensusWaveMem<KMAX>& M = mem[threadIdx.x / WAVE];
   const int lane = lane_id();
-  unsigned long long* queue = A.counts + 2 * (long long)A.n_pairs;
+  unsigned long long* queue = A.queue;
   const long long n_tasks = A.pair_prefix[A.n_pairs];
   for (;;) {
     long long t0 = 0;
@@ -1210,15 +1223,20 @@ __global__ __launch_bounds__(BLOCK) void k_census(CensusArgs A) {
       const Plan& plan = A.plans[pr.plan];
       const long long local = t - A.pair_prefix[pi];
       Acc acc{0ull, 0ull};
-      switch (plan.k) {
-        case 2: census_task<2>(g, plan, M.m2, pr, local, acc); break;
-        case 3: census_task<3>(g, plan, M.m3, pr, local, acc); break;
-        case 4: census_task<4>(g, plan, M.m4, pr, local, acc); break;
-        default: census_task<5>(g, plan, M.m5, pr, local, acc); break;
+      if constexpr (KMAX == 5) {
+        switch (plan.k) {
+          case 2: census_task<2>(g, plan, M.m2, pr, local, acc); break;
+          case 3: census_task<3>(g, plan, M.m3, pr, local, acc); break;
+          case 4: census_task<4>(g, plan, M.m4, pr, local, acc); break;
+          default: census_task<5>(g, plan, M.m5, pr, local, acc); break;
+        }
+      } else {
+        if (plan.k == 6) census_task<6>(g, plan, M.m6, pr, local, acc);
+        else census_task<7>(g, plan, M.m7, pr, local, acc);
       }
       unsigned long long l, h;
       wave_sum_u128(acc.cnt, &l, &h);
-      if (lane == 0 && (l | h)) add_u128(A.counts + 2 * (long long)pi, l, h);
+      if (lane == 0 && (l | h)) add_u128(A.counts + 2 * (long long)pr.out, l, h);
     }
   }
 }
@@ -1875,14 +1893,18 @@ struct gz_census_impl {
   hipStream_t stream = nullptr;
   dev::Graph* d_graphs = nullptr;
   Plan* d_plans = nullptr;
-  dev::CensusPair* d_pairs = nullptr;
-  long long* d_pair_prefix = nullptr;
-  unsigned long long* d_counts = nullptr;
+  // per size class (patterns of 2-5 and of 6-7 vertices): pair table,
+  // task prefix and launch size
+  dev::CensusPair* d_pairs[2] = {nullptr, nullptr};
+  long long* d_pair_prefix[2] = {nullptr, nullptr};
+  int n_class_pairs[2] = {0, 0};
+  long long class_tasks[2] = {0, 0};
+  int class_grid[2] = {0, 0};
+  unsigned long long* d_counts = nullptr;  // 2 per pair, then 2 queue heads
   int n_pairs = 0;
   long long n_tasks = 0;
   // defaults: the tuner's pick on the smallest graphs of the 64-graph batch
   int chunk3 = 128, chunk45 = 1, batch = 1;
-  int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1892,10 +1914,12 @@ static void census_release_tables(gz_census_impl* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->exec = nullptr;
   c->graph = nullptr;
-  if (c->d_pairs) (void)hipFree(c->d_pairs);
-  if (c->d_pair_prefix) (void)hipFree(c->d_pair_prefix);
-  c->d_pairs = nullptr;
-  c->d_pair_prefix = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (c->d_pairs[k]) (void)hipFree(c->d_pairs[k]);
+    if (c->d_pair_prefix[k]) (void)hipFree(c->d_pair_prefix[k]);
+    c->d_pairs[k] = nullptr;
+    c->d_pair_prefix[k] = nullptr;
+  }
 }
 
 // Pair table and prefix for the current tuning, then capture the zeroing of
@@ -1903,8 +1927,8 @@ static void census_release_tables(gz_census_impl* c) {
 static gz_status census_build(gz_census_impl* c) {
   census_release_tables(c);
   const int ng = (int)c->graphs.size(), ns = (int)c->scheds.size();
-  std::vector<dev::CensusPair> pairs((size_t)ng * ns);
-  std::vector<long long> prefix((size_t)ng * ns + 1, 0);
+  std::vector<dev::CensusPair> pairs[2];
+  std::vector<long long> prefix[2] = {{0}, {0}};
   for (int gi = 0; gi < ng; ++gi)
     for (int si = 0; si < ns; ++si) {
       const Plan& pl = c->scheds[si]->plan;
@@ -1913,31 +1937,50 @@ static gz_status census_build(gz_census_impl* c) {
       DevTasks dt;
       gz_status rc = graph_tasks(c->graphs[gi], b1, chunk, c->stream, &dt);
       if (rc) return rc;
-      const int pi = gi * ns + si;
-      pairs[pi] = dev::CensusPair{dt.prefix, gi, si, chunk, b1 ? 1 : 0};
-      prefix[pi + 1] = prefix[pi] + dt.n_tasks;
+      const int cls = pl.k <= 5 ? 0 : 1;
+      pairs[cls].push_back(dev::CensusPair{dt.prefix, gi, si, chunk, b1 ? 1 : 0, gi * ns + si});
+      prefix[cls].push_back(prefix[cls].back() + dt.n_tasks);
     }
   c->n_pairs = ng * ns;
-  c->n_tasks = prefix.back();
-  GZ_HIP(hipMalloc(&c->d_pairs, sizeof(dev::CensusPair) * pairs.size()));
-  GZ_HIP(hipMalloc(&c->d_pair_prefix, sizeof(long long) * prefix.size()));
-  GZ_HIP(hipMemcpy(c->d_pairs, pairs.data(), sizeof(dev::CensusPair) * pairs.size(),
-                   hipMemcpyHostToDevice));
-  GZ_HIP(hipMemcpy(c->d_pair_prefix, prefix.data(), sizeof(long long) * prefix.size(),
-                   hipMemcpyHostToDevice));
-  int per_cu = 0, cus = 0;
-  GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::k_census, dev::BLOCK, 0));
+  c->n_tasks = prefix[0].back() + prefix[1].back();
+  int cus = 0;
   GZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  long long need = (c->n_tasks + (long long)c->batch * dev::WPB - 1) / ((long long)c->batch * dev::WPB);
-  c->grid = (int)std::max(1ll, std::min((long long)std::max(per_cu, 1) * std::max(cus, 1), need));
-  const long long n_acc = 2LL * c->n_pairs + 1;
-  dev::CensusArgs args{c->d_graphs, c->d_plans, c->d_pairs, c->d_pair_prefix, c->n_pairs,
-                       c->batch, c->d_counts};
+  for (int cls = 0; cls < 2; ++cls) {
+    c->n_class_pairs[cls] = (int)pairs[cls].size();
+    c->class_tasks[cls] = prefix[cls].back();
+    if (pairs[cls].empty()) continue;
+    GZ_HIP(hipMalloc(&c->d_pairs[cls], sizeof(dev::CensusPair) * pairs[cls].size()));
+    GZ_HIP(hipMalloc(&c->d_pair_prefix[cls], sizeof(long long) * prefix[cls].size()));
+    GZ_HIP(hipMemcpy(c->d_pairs[cls], pairs[cls].data(),
+                     sizeof(dev::CensusPair) * pairs[cls].size(), hipMemcpyHostToDevice));
+    GZ_HIP(hipMemcpy(c->d_pair_prefix[cls], prefix[cls].data(),
+                     sizeof(long long) * prefix[cls].size(), hipMemcpyHostToDevice));
+    int per_cu = 0;
+    if (cls == 0)
+      GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::k_census<5>, dev::BLOCK, 0));
+    else
+      GZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::k_census<7>, dev::BLOCK, 0));
+    const long long need = (c->class_tasks[cls] + (long long)c->batch * dev::WPB - 1) /
+                           ((long long)c->batch * dev::WPB);
+    c->class_grid[cls] =
+        (int)std::max(1ll, std::min((long long)std::max(per_cu, 1) * std::max(cus, 1), need));
+  }
+  const long long n_acc = 2LL * c->n_pairs + 2;
+  unsigned long long* queues = c->d_counts + 2LL * c->n_pairs;
   GZ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
                      dim3(256), 0, c->stream, c->d_counts, n_acc);
-  if (c->n_tasks > 0)
-    hipLaunchKernelGGL(dev::k_census, dim3((unsigned)c->grid), dim3(dev::BLOCK), 0, c->stream, args);
+  for (int cls = 0; cls < 2; ++cls) {
+    if (c->class_tasks[cls] <= 0) continue;
+    dev::CensusArgs args{c->d_graphs, c->d_plans, c->d_pairs[cls], c->d_pair_prefix[cls],
+                         c->n_class_pairs[cls], c->batch, c->d_counts, queues + cls};
+    if (cls == 0)
+      hipLaunchKernelGGL(dev::k_census<5>, dim3((unsigned)c->class_grid[cls]), dim3(dev::BLOCK), 0,
+                         c->stream, args);
+    else
+      hipLaunchKernelGGL(dev::k_census<7>, dim3((unsigned)c->class_grid[cls]), dim3(dev::BLOCK), 0,
+                         c->stream, args);
+  }
   hipError_t e = hipStreamEndCapture(c->stream, &c->graph);
   if (e != hipSuccess) {
     set_error(std::string("census graph capture: ") + hipGetErrorString(e));
@@ -1983,8 +2026,8 @@ gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
     }
   }
   for (int i = 0; i < n_scheds && !rc; ++i) {
-    if (!scheds[i] || scheds[i]->plan.k > 5) {
-      set_error("census patterns must have at most 5 vertices");
+    if (!scheds[i] || scheds[i]->plan.k > 7) {
+      set_error("census patterns must have at most 7 vertices");
       rc = scheds[i] ? GZ_ENOTSUP : GZ_EINVAL;
     }
   }
@@ -1998,7 +2041,7 @@ gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
     if (hipStreamCreate(&c->stream) != hipSuccess ||
         hipMalloc(&c->d_graphs, sizeof(dev::Graph) * gt.size()) != hipSuccess ||
         hipMalloc(&c->d_plans, sizeof(Plan) * pt.size()) != hipSuccess ||
-        hipMalloc(&c->d_counts, sizeof(unsigned long long) * (2 * (size_t)n_graphs * n_scheds + 1)) !=
+        hipMalloc(&c->d_counts, sizeof(unsigned long long) * (2 * (size_t)n_graphs * n_scheds + 2)) !=
             hipSuccess ||
         hipMemcpy(c->d_graphs, gt.data(), sizeof(dev::Graph) * gt.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
