@@ -907,8 +907,12 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
         atomicOr(&filt[hx >> 5], 1u << (hx & 31));
         int len;
         row_plan(g, x, a, &urs[a], &ulen[a], &slot[a], &len);
-        pref[a] = len;
-        mysum += len;
+        // rows of at least a wave's length are probed one wave per row
+        // (coalesced, no search for the row); the others are flattened
+        const int flat = len < WAVE ? len : 0;
+        if (len >= WAVE) slot[a] |= 2;
+        pref[a] = flat;
+        mysum += flat;
       }
     }
     int wtot;
@@ -930,6 +934,28 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
       }
     }
     __syncthreads();
+    for (int a = wv; a < d; a += CWPB) {
+      const int sl = slot[a];
+      if (!(sl & 2)) continue;
+      const int len = (sl & 1) ? ulen[a] : a;
+      for (int e = lane; e < len; e += WAVE) {
+        int bit = -1;
+        if (!(sl & 1)) {
+          bit = contains(g.col + urs[a], ulen[a], xs[e]) ? e : -1;
+        } else {
+          const int32_t y = g.col[urs[a] + e];
+          const uint32_t hy = filt_hash(y);
+          if ((filt[hy >> 5] >> (hy & 31)) & 1u) {
+            const int q = lower_bound(xs, a, y);
+            bit = (q < a && xs[q] == y) ? q : -1;
+          }
+        }
+        if (bit >= 0) atomicOr(&rows[a * W + (bit >> 6)], 1ull << (bit & 63));
+      }
+    }
+    // short rows: (row, element) pairs flattened over the block; rows of
+    // length 0 in the prefix (the long ones) are never the last row at or
+    // below a pair's index
     for (int p = tid; p < total; p += CBLOCK) {
       int lo2 = 0, hi2 = d;
       while (lo2 < hi2) {
