@@ -41,7 +41,7 @@ enum {
     GZ_ENOMEM = -2,      /* host or device allocation failed                  */
     GZ_EDEVICE = -3,     /* a HIP runtime call failed                          */
     GZ_EOVERFLOW = -4,   /* the exact count does not fit in 64 bits            */
-    GZ_ENOTSUP = -5      /* supported by the interface, not by this build      */
+    GZ_ENOTSUP = -5      /* valid request outside what the library handles    */
 };
 
 typedef struct gz_graph gz_graph;
