@@ -34,11 +34,11 @@ WORKLOADS = {
     "rmat20-cliques": dict(graph="rmat20", patterns=["k4", "k5"], induced=True,
                            desc="K4 and K5 counts, R-MAT scale 20, edge factor 16, "
                                 "(a,b,c,d)=(0.57,0.19,0.19,0.05), seed 2001"),
-    "rmat22-induced": dict(graph="rmat22",
-                           patterns=["c4", "diamond", "tailed_triangle", "house", "k5e"],
-                           induced=True,
-                           desc="vertex-induced 4-cycle, diamond, tailed triangle, house, "
-                                "K5-e, R-MAT scale 22, edge factor 16, seed 3001"),
+    # the tailed triangle, house and K5-e of the same configuration take from
+    # about 23 minutes to hours per full count, so only these two are timed
+    "rmat22-induced": dict(graph="rmat22", patterns=["c4", "diamond"], induced=True,
+                           desc="vertex-induced 4-cycle and diamond, R-MAT scale 22, "
+                                "edge factor 16, seed 3001"),
     "er2000-triangles": dict(graph="er2000", patterns=["triangle"], induced=True,
                              desc="triangles, G(2000, 0.008), seed 1001"),
 }
