@@ -1,0 +1,24 @@
+"""bench.py's command-line contract on the CPU: more than one GPU is refused
+with a message, and the workload table names only known graphs."""
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_workloads_name_known_graphs():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1911_12877_amd import synth
+    for name, wl in bench.WORKLOADS.items():
+        assert wl["graph"] in synth.CONFIGS, name
+        assert wl["patterns"], name
