@@ -81,7 +81,7 @@ gz_status gz_load_graph(const int32_t* rowptr, const int32_t* colidx,
  * list may hold self-loops, duplicates and one or both orientations of an
  * edge; it is always normalised (GZ_GRAPH_NORMALIZE is implied).  With
  * GZ_GRAPH_PREP_DEVICE the normalisation and the degree reindex run on the
- * current device (m <= 2^31) and the prepared graph is copied back to the
+ * current device (m < 2^31) and the prepared graph is copied back to the
  * handle's host copy; the arrays are the same as those of the host path.
  * Errors: GZ_EINVAL (n < 0, m < 0, an endpoint outside [0, n), a result of
  * 2^31 or more entries, unknown flags), GZ_ENOMEM, GZ_EDEVICE.

@@ -172,8 +172,8 @@ gz_status device_prepare_edges(const int32_t* src, const int32_t* dst, int64_t m
     set_error("n or m out of range");
     return GZ_EINVAL;
   }
-  if (m > (int64_t)1 << 31) {
-    set_error("device preparation takes at most 2^31 input edges");
+  if (m >= (int64_t)1 << 31) {  // 2m keys must fit the 32-bit offsets of the unique pass
+    set_error("device preparation takes fewer than 2^31 input edges");
     return GZ_EINVAL;
   }
   Scratch s;
