@@ -9,6 +9,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -28,9 +29,10 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     objs = []
+    cmds = []
     incs = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for src in SOURCES:
         path = os.path.join(CSRC, src)
@@ -43,8 +45,14 @@ def build(verbose: bool = False) -> str:
                 incs + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # translation units compile independently; the largest first
+    order = sorted(range(len(cmds)), key=lambda i: -os.path.getsize(
+        os.path.join(CSRC, SOURCES[i])))
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as pool:
+        for f in [pool.submit(subprocess.check_call, cmds[i]) for i in order]:
+            f.result()
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
