@@ -167,6 +167,10 @@ def test_forced_inclusion_exclusion_per_root(nm):
     with _env(GZ_IE_FORCE=1):
         got = gz.count_roots(G, s, roots)
     assert np.array_equal(got, want)
+    # with every prefix split as well
+    with _env(GZ_IE_FORCE=1, GZ_SPLIT_MIN_LEN=0):
+        got = gz.count_roots(G, s, roots)
+    assert np.array_equal(got, want)
 
 
 def test_larger_patterns_forced_inclusion_exclusion():
