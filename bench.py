@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # 32-bit integer VALU: 256 CUs x 64 lanes per clock x 2.4 GHz (the FP32
 # vector figure of 157.3 TFLOP/s counts packed pairs and FMA as two each)
 ALU_PEAK_GOPS = 256 * 64 * 2.4
+# wave64 VALU instructions issued per second: one per CU per clock
+VALU_ISSUE_PEAK = 256 * 2.4e9
 
 WORKLOADS = {
     "rmat20-cliques": dict(graph="rmat20", patterns=["k4", "k5"], induced=True,
@@ -69,6 +71,19 @@ def load_traffic(workload, kernel):
     if not rec or rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def load_valu_insts(workload, kernel):
+    """VALU wave instructions per launch of `kernel` from a committed rocprof
+    counter run (SQ_INSTS_VALU), or None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload, {}).get(kernel)
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("valu_insts_per_launch")
 
 
 def cpu_baseline(edges, pattern_names, induced, orders, bounds, target_s):
@@ -250,9 +265,12 @@ def main():
         ops = None
     if ops is not None:
         achieved = ops / (avg_ms[dom] / 1e3) / 1e9
+        valu = load_valu_insts(args.workload, wl["patterns"][dom])
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_GOPS,
                     "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4),
                     "traffic": traffic, "ops_per_launch": ops,
+                    "valu_issue_frac": (round(valu / (avg_ms[dom] / 1e3) / VALU_ISSUE_PEAK, 4)
+                                        if valu else None),
                     "kernel": f"k_clique_wave<{kdom}> + k_clique_block<{kdom}>",
                     "pattern": wl["patterns"][dom], "kernel_ms": round(avg_ms[dom], 4)}
     else:
