@@ -697,7 +697,9 @@ __device__ __forceinline__ int select64(unsigned long long x, int r) {
 // 5-cliques of the root through the edge (C1[a], C1[b]), b < a, b in word
 // wb: the sum over c in m = row a AND row b of popcount(m AND row c).  The
 // first four words of m stay in registers, so each c costs one LDS read per
-// word in the common case instead of three.
+// word in the common case instead of three; members are scanned in 32-bit
+// halves, since the kernel is bound by VALU issue and 64-bit bit scans and
+// clears take twice the instructions.
 __device__ __forceinline__ unsigned long long k5_edge(const unsigned long long* rows, int W,
                                                       int a, int b, int wb) {
   const unsigned long long* ra = rows + (size_t)a * W;
@@ -706,39 +708,45 @@ __device__ __forceinline__ unsigned long long k5_edge(const unsigned long long* 
   const unsigned long long m1 = wb >= 1 ? (ra[1] & rb[1]) : 0ull;
   const unsigned long long m2 = wb >= 2 ? (ra[2] & rb[2]) : 0ull;
   const unsigned long long m3 = wb >= 3 ? (ra[3] & rb[3]) : 0ull;
-  unsigned long long total = 0;
+  unsigned int total = 0;  // at most |C1|^2 members per edge
   for (int wc = 0; wc <= wb; ++wc) {
-    unsigned long long mc = wc == 0 ? m0 : wc == 1 ? m1 : wc == 2 ? m2 : wc == 3 ? m3
+    const unsigned long long mw = wc == 0 ? m0 : wc == 1 ? m1 : wc == 2 ? m2 : wc == 3 ? m3
                                                                              : (ra[wc] & rb[wc]);
-    // two members c per iteration: their row loads are independent
-    while (mc) {
-      const int c1 = wc * 64 + __builtin_ctzll(mc);
-      mc &= mc - 1;
-      const bool two = mc != 0ull;
-      const int c2 = two ? wc * 64 + __builtin_ctzll(mc) : c1;
-      if (two) mc &= mc - 1;
-      const unsigned long long* r1 = rows + (size_t)c1 * W;
-      const unsigned long long* r2 = rows + (size_t)c2 * W;
-      unsigned int n1 = (unsigned)__popcll(m0 & r1[0]);
-      unsigned int n2 = (unsigned)__popcll(m0 & r2[0]);
-      if (wc >= 1) {
-        n1 += (unsigned)__popcll(m1 & r1[1]);
-        n2 += (unsigned)__popcll(m1 & r2[1]);
+    // members in 32-bit halves: bit scans and clears stay 32-bit
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      unsigned int mc = half ? (unsigned int)(mw >> 32) : (unsigned int)mw;
+      const int cbase = wc * 64 + half * 32;
+      // two members c per iteration: their row loads are independent
+      while (mc) {
+        const int c1 = cbase + __builtin_ctz(mc);
+        mc &= mc - 1;
+        const bool two = mc != 0u;
+        const int c2 = two ? cbase + __builtin_ctz(mc) : c1;
+        if (two) mc &= mc - 1;
+        const unsigned long long* r1 = rows + (size_t)c1 * W;
+        const unsigned long long* r2 = rows + (size_t)c2 * W;
+        unsigned int n1 = (unsigned)__popcll(m0 & r1[0]);
+        unsigned int n2 = (unsigned)__popcll(m0 & r2[0]);
+        if (wc >= 1) {
+          n1 += (unsigned)__popcll(m1 & r1[1]);
+          n2 += (unsigned)__popcll(m1 & r2[1]);
+        }
+        if (wc >= 2) {
+          n1 += (unsigned)__popcll(m2 & r1[2]);
+          n2 += (unsigned)__popcll(m2 & r2[2]);
+        }
+        if (wc >= 3) {
+          n1 += (unsigned)__popcll(m3 & r1[3]);
+          n2 += (unsigned)__popcll(m3 & r2[3]);
+        }
+        for (int j = 4; j <= wc; ++j) {
+          const unsigned long long m = ra[j] & rb[j];
+          n1 += (unsigned)__popcll(m & r1[j]);
+          n2 += (unsigned)__popcll(m & r2[j]);
+        }
+        total += n1 + (two ? n2 : 0u);
       }
-      if (wc >= 2) {
-        n1 += (unsigned)__popcll(m2 & r1[2]);
-        n2 += (unsigned)__popcll(m2 & r2[2]);
-      }
-      if (wc >= 3) {
-        n1 += (unsigned)__popcll(m3 & r1[3]);
-        n2 += (unsigned)__popcll(m3 & r2[3]);
-      }
-      for (int j = 4; j <= wc; ++j) {
-        const unsigned long long m = ra[j] & rb[j];
-        n1 += (unsigned)__popcll(m & r1[j]);
-        n2 += (unsigned)__popcll(m & r2[j]);
-      }
-      total += n1 + (two ? n2 : 0u);
     }
   }
   return total;
