@@ -189,8 +189,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1911_12877_amd import gz, synth
-    from oracle import patterns as P  # pattern adjacency tables only
+    from paper_1911_12877_amd import gz, motifs, synth
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
@@ -213,7 +212,7 @@ def main():
     log(f"prepared graph n={info['n']} nnz={info['nnz']} max_deg={info['max_deg']} "
         f"max_lo={info['max_lo_deg']} in {t_prep:.2f}s")
 
-    adjs = [np.array(P.named(nm), dtype=np.uint8) for nm in wl["patterns"]]
+    adjs = [motifs.named(nm) for nm in wl["patterns"]]
     scheds = [gz.compile_pattern(a, wl["induced"]) for a in adjs]
     infos = [s.info() for s in scheds]
     alg_bytes = []

@@ -71,3 +71,42 @@ def connected_patterns(k):
     if not 2 <= k <= 7:
         raise ValueError("pattern size must be between 2 and 7")
     return [from_code(k, c) for c in _codes(k)]
+
+
+def _adj(k, edges):
+    a = np.zeros((k, k), dtype=np.uint8)
+    for u, v in edges:
+        a[u, v] = a[v, u] = 1
+    return a
+
+
+def named(name):
+    """Adjacency (uint8) of a named pattern: 'triangle', 'diamond' (K4 minus
+    the edge {2,3}), 'tailed_triangle' (triangle 0-1-2 with 3 joined to 0),
+    'house' (4-cycle 0-1-2-3 with 4 joined to 0 and 1), 'k<n>', 'k<n>e' (K_n
+    minus the edge {n-2, n-1}), 'c<n>' (cycle), 'p<n>' (path), 'star<n>' (hub
+    0 and n-1 leaves), 'c6chord03' / 'c6chord02' (6-cycle with the chord
+    {0,3} / {0,2})."""
+    ring = lambda n: [(i, (i + 1) % n) for i in range(n)]
+    fixed = {
+        "triangle": (3, [(0, 1), (1, 2), (0, 2)]),
+        "diamond": (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3)]),
+        "tailed_triangle": (4, [(0, 1), (1, 2), (0, 2), (0, 3)]),
+        "house": (5, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (1, 4)]),
+        "c6chord03": (6, ring(6) + [(0, 3)]),
+        "c6chord02": (6, ring(6) + [(0, 2)]),
+    }
+    if name in fixed:
+        return _adj(*fixed[name])
+    for prefix, make in (("star", lambda n: [(0, i) for i in range(1, n)]),
+                         ("k", lambda n: [(i, j) for i in range(n) for j in range(i + 1, n)]),
+                         ("c", ring),
+                         ("p", lambda n: [(i, i + 1) for i in range(n - 1)])):
+        rest = name[len(prefix):]
+        if name.startswith(prefix) and rest.isdigit():
+            return _adj(int(rest), make(int(rest)))
+    if name.startswith("k") and name.endswith("e") and name[1:-1].isdigit():
+        n = int(name[1:-1])
+        return _adj(n, [(i, j) for i in range(n) for j in range(i + 1, n)
+                        if (i, j) != (n - 2, n - 1)])
+    raise KeyError(name)
