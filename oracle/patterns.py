@@ -217,13 +217,15 @@ def forest_pass_rate(bound, upto):
     return r
 
 
-def analytic_cost(adj, schedule, induced, n=1000, avg_deg=5.0):
-    """Section 5.4: expected loop iterations in G(n, p) summed over loops."""
+def level_iterations(adj, schedule, induced, n=1000, avg_deg=5.0):
+    """Section 5.4: expected iterations of each loop i in G(n, p), i.e. the
+    product of the loop sizes up to i times the restriction pass rate up to
+    i.  Returned per loop, in schedule order."""
     adj = as_adj(adj)
     k = len(schedule)
     p = avg_deg / (n - 1)
     bound = reduced_bounds(adj, schedule)
-    total = 0.0
+    out = []
     prod = 1.0
     for i in range(k):
         if i == 0:
@@ -233,7 +235,15 @@ def analytic_cost(adj, schedule, induced, n=1000, avg_deg=5.0):
             d = (i - c) if induced else 0
             size = n * (p ** c) * ((1.0 - p) ** d)
         prod *= size
-        total += prod * forest_pass_rate(bound, i)
+        out.append(prod * forest_pass_rate(bound, i))
+    return out
+
+
+def analytic_cost(adj, schedule, induced, n=1000, avg_deg=5.0):
+    """Section 5.4: expected loop iterations in G(n, p) summed over loops."""
+    total = 0.0
+    for it in level_iterations(adj, schedule, induced, n, avg_deg):
+        total += it
     return total
 
 

@@ -304,3 +304,64 @@ def test_instrument_triangle_closed_form():
     b, c = oracle.instrument(g, tri, True, (0, 1, 2), [-1, 0, 1])
     assert b == want
     assert c == oracle.count(g, tri)
+
+
+def test_instrument_induced_c4_by_definition():
+    """Induced 4-cycle 0-1-2-3-0, schedule (0, 1, 3, 2), bounds v1 < v0,
+    v2 < v1, v3 < v0, counted from the definition of the algorithmic bytes:
+    every evaluation of loop i reads, for each list of its set expression
+    (pattern neighbours intersected, non-neighbours subtracted), the part
+    below the loop's bound (4 B per element) and the row's two offsets (8 B).
+    Loop 1: N(v0) below v0.  Loop 2 (pattern vertex 3): N(v0) and N(v1)
+    below v1.  Loop 3 (pattern vertex 2): N(v0), N(v1) and N(v2) below v0.
+    No loop extends the enclosing one's set (loop 3 is bounded by loop 0)."""
+    e = synth.chung_lu_edges(250, 2.3, 10.0, 73, cap=True)
+    g = oracle.from_edge_tuple(e)
+    nb = [g.col[g.rowptr[v]:g.rowptr[v + 1]] for v in range(g.n)]
+    ns = [set(r.tolist()) for r in nb]
+
+    def below(v, b):
+        return int(np.sum(nb[v] < b))
+
+    want = 0
+    count = 0
+    for v0 in range(g.n):
+        want += 4 * below(v0, v0) + 8
+        for v1 in nb[v0][nb[v0] < v0].tolist():
+            want += 4 * (below(v0, v1) + below(v1, v1)) + 16
+            for v2 in nb[v0][nb[v0] < v1].tolist():
+                if v2 in ns[v1]:
+                    continue
+                want += 4 * (below(v0, v0) + below(v1, v0) + below(v2, v0)) + 24
+                count += sum(1 for x in ns[v1] & ns[v2] if x < v0 and x not in ns[v0])
+    c4 = P.named("c4")
+    b, c = oracle.instrument(g, c4, True, (0, 1, 3, 2), [-1, 0, 1, 0])
+    assert c == count == oracle.count(g, c4)
+    assert b == want
+
+
+def test_instrument_induced_tailed_triangle_by_definition():
+    """Induced tailed triangle (triangle 0-1-2, tail 3 on 0), schedule
+    (1, 2, 0, 3), one bound v1 < v0.  Loop 1: N(v0) below v0.  Loop 2
+    (pattern vertex 0, unbounded): all of N(v0) and N(v1).  Loop 3 (the tail,
+    unbounded): all of N(v2) intersected and, vertex-induced, all of N(v0)
+    and N(v1) subtracted."""
+    e = synth.chung_lu_edges(250, 2.3, 10.0, 74, cap=True)
+    g = oracle.from_edge_tuple(e)
+    nb = [g.col[g.rowptr[v]:g.rowptr[v + 1]] for v in range(g.n)]
+    ns = [set(r.tolist()) for r in nb]
+    deg = [len(r) for r in nb]
+    want = 0
+    count = 0
+    for v0 in range(g.n):
+        want += 4 * int(np.sum(nb[v0] < v0)) + 8
+        for v1 in nb[v0][nb[v0] < v0].tolist():
+            want += 4 * (deg[v0] + deg[v1]) + 16
+            for v2 in sorted(ns[v0] & ns[v1]):
+                want += 4 * (deg[v0] + deg[v1] + deg[v2]) + 24
+                count += sum(1 for x in ns[v2]
+                             if x not in (v0, v1) and x not in ns[v0] and x not in ns[v1])
+    tt = P.named("tailed_triangle")
+    b, c = oracle.instrument(g, tt, True, (1, 2, 0, 3), [-1, 0, -1, -1])
+    assert c == count == oracle.count(g, tt)
+    assert b == want

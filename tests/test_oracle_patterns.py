@@ -230,3 +230,90 @@ def test_bf16_rounding_oracle():
     assert mlp.bf16(np.array([one_plus]))[0] == 1.0
     up = np.float32(1.0) + np.float32(3 * 2 ** -9)     # nearer 1+2^-7
     assert mlp.bf16(np.array([up]))[0] == 1.0 + 2 ** -7
+
+
+def test_adam_oracle_first_step_closed_form():
+    """From zero moments the bias corrections cancel exactly: the first step
+    moves every parameter by -lr g / (|g| + eps).  The tiny gradient pins
+    where eps sits (outside the square root: 1e-8 / (1e-8 + 1e-8) = 1/2)."""
+    import numpy as np
+    from oracle import mlp
+    g = np.array([0.5, -2.0, 1e-8, 3.0])
+    p0 = np.array([1.0, 2.0, 3.0, 4.0])
+    z = np.zeros(4)
+    p1, m1, v1 = mlp.adam(p0, g, z, z, lr=0.01, step=1)
+    assert np.allclose(m1, 0.1 * g, rtol=1e-15, atol=0)
+    assert np.allclose(v1, 0.001 * g * g, rtol=1e-15, atol=0)
+    assert p1[2] == pytest.approx(3.0 - 0.005, rel=1e-15)
+    assert p1[0] == pytest.approx(1.0 - 0.01 * 0.5 / (0.5 + 1e-8), rel=1e-15)
+    assert p1[1] == pytest.approx(2.0 + 0.01 * 2.0 / (2.0 + 1e-8), rel=1e-15)
+    # a constant gradient keeps the corrected moments at g and g^2: every
+    # step is the same
+    p, m, v = p0, z, z
+    for step in range(1, 6):
+        q, m, v = mlp.adam(p, g, m, v, lr=0.01, step=step)
+        assert np.allclose(q - p, p1 - p0, rtol=1e-9, atol=0)
+        p = q
+
+
+def test_adam_oracle_second_step_by_hand():
+    """Gradients 1 then -2, lr 0.1, beta1 0.9, beta2 0.999, eps 1e-8, from 0:
+    m2 = 0.9*0.1 - 0.2 = -0.11, v2 = 0.999*0.001 + 0.004 = 0.004999;
+    corrected -0.11/0.19 and 0.004999/0.001999 = 2.5007503751875938;
+    p2 = -0.1/(1 + 1e-8) + 0.1 * 0.5789473684210526 / (1.5813761017504956 + 1e-8)
+       = -0.06338964652792491 (decimal arithmetic, 40 digits)."""
+    import numpy as np
+    from oracle import mlp
+    z = np.zeros(1)
+    p1, m1, v1 = mlp.adam(z, np.array([1.0]), z, z, lr=0.1, step=1)
+    assert p1[0] == pytest.approx(-0.09999999900000001, rel=1e-15)
+    p2, m2, v2 = mlp.adam(p1, np.array([-2.0]), m1, v1, lr=0.1, step=2)
+    assert m2[0] == pytest.approx(-0.11, rel=1e-14)
+    assert v2[0] == pytest.approx(0.004999, rel=1e-14)
+    assert p2[0] == pytest.approx(-0.06338964652792491, rel=1e-13)
+
+
+def test_analytic_cost_red_edge_factor_by_hand():
+    """Induced path P3 (centre 0, leaves 1 and 2), schedule (0, 1, 2), bound
+    v2 < v1: loop 1 has n p iterations per root, loop 2 n p (1-p) (one black,
+    one red earlier neighbour), halved by the bound:
+    cost = n + n^2 p + n^3 p^2 (1-p) / 2 = 18467.354679441641 at n = 1000,
+    p = 5/999; without the red factor (edge-induced) 18530.042555067580."""
+    a = P.from_edges(3, [(0, 1), (0, 2)])
+    assert P.reduced_bounds(a, (0, 1, 2)) == [-1, -1, 1]
+    assert P.analytic_cost(a, (0, 1, 2), True) == pytest.approx(18467.354679441641, rel=1e-13)
+    assert P.analytic_cost(a, (0, 1, 2), False) == pytest.approx(18530.042555067580, rel=1e-13)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_analytic_last_loop_is_expected_instances(k):
+    """The last loop's iterations in the model are the expected number of
+    instances in G(n, p), with n^k in place of n (n-1)...(n-k+1): each of the
+    m pattern edges present (p), each of the C(k,2) - m non-edges absent
+    (1 - p, vertex-induced only), each instance found once (1/|Aut|).  A red
+    factor dropped or counted on the wrong loops changes the exponent of
+    (1 - p) and fails here for every non-clique pattern."""
+    n, pr = 1000, 5.0 / 999
+    for a in P.connected_patterns(k):
+        m = sum(a[i][j] for i in range(k) for j in range(i + 1, k))
+        aut = len(P.automorphisms(a))
+        for s in P.distinct_schedules(a):
+            for induced in (True, False):
+                red = (k * (k - 1) // 2 - m) if induced else 0
+                want = n ** k * pr ** m * (1 - pr) ** red / aut
+                got = P.level_iterations(a, s, induced)[-1]
+                assert got == pytest.approx(want, rel=1e-12), (a, s, induced)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_explorer_emits_lexicographic_class_minima(k):
+    """A second formulation of Algorithm 3's output: group the brute-force
+    valid schedules (Algorithm 2) into classes under the automorphisms and
+    keep each class's lexicographically smallest member; the explorer emits
+    exactly these, in lexicographic order (the order the analytic pick's
+    tie-break relies on)."""
+    for a in P.connected_patterns(k):
+        auts = P.automorphisms(a)
+        valid = P.valid_schedules_bruteforce(a)
+        minima = sorted({min(tuple(x[v] for v in s) for x in auts) for s in valid})
+        assert P.distinct_schedules(a) == minima
