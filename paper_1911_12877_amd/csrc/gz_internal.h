@@ -135,6 +135,19 @@ struct CliqueLists {
   int64_t bucket_begin[5] = {0, 0, 0, 0, 0};
 };
 
+// Dense neighbour bitmaps of the leading vertices 0..n_hub-1, which after
+// the degree reindex are the vertices of highest degree: bit x of row v is
+// set when x is a neighbour of v.  A membership probe into a hub's list is
+// then one load instead of a binary search.  Row v starts at word
+// v * row_words (32-bit words, row_words = ceil(n / 32)).
+struct HubMaps {
+  int32_t min_deg = 0;        // vertices of at least this degree get a row
+  long long cap_bytes = 0;    // and at most this many bytes in total
+  int32_t n_hub = 0;
+  long long row_words = 0;
+  uint32_t* bits = nullptr;   // device, n_hub * row_words words
+};
+
 void set_error(const std::string& msg);
 
 }  // namespace gz
@@ -157,6 +170,8 @@ struct gz_graph {
   // clique-path root lists over all roots, built on first use
   mutable bool clique_ready = false;
   mutable gz::CliqueLists clique_all;
+  // hub bitmaps by (min_deg, cap_bytes), built on first use
+  mutable std::vector<gz::HubMaps> hub_cache;
 };
 
 struct gz_schedule {

@@ -48,6 +48,10 @@ struct Graph {
   const int32_t* __restrict__ col;
   const int32_t* __restrict__ lo;
   int32_t n;
+  // neighbour bitmaps of vertices 0..n_hub-1 (none when n_hub == 0)
+  const uint32_t* __restrict__ hub;
+  int32_t n_hub;
+  long long hub_words;
 };
 
 struct HeavyItem;
@@ -133,6 +137,17 @@ template <typename P>
 __device__ __forceinline__ bool contains(P a, int len, int32_t x) {
   int i = lower_bound(a, len, x);
   return i < len && a[i] == x;
+}
+
+// Is x in the list of v, given as its row cut to the first len entries?
+// Every caller probes with an x below the cut's bound (x comes from a list
+// cut at the same bound), so membership in the cut is membership in N(v):
+// one bit of v's bitmap when v is a hub, else a binary search of the cut.
+__device__ __forceinline__ bool has_nb(const Graph& g, int32_t v, const int32_t* row, int len,
+                                       int32_t x) {
+  if (v < g.n_hub)
+    return (g.hub[(long long)v * g.hub_words + (x >> 5)] >> (x & 31)) & 1u;
+  return contains(row, len, x);
 }
 
 // number of entries of the row (start, deg) below bound B; `own` when B is
@@ -259,8 +274,9 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
           if ((neg >> j) & 1u)
             len[j] = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
         if ((neg >> J) & 1u) len[J] = bounded_len(g, u, urs, urd, B, item_bound);
-        // walk length of the inclusion-exclusion terms
-        long long cost = n_pos > 1 ? blen : 0;
+        // walk length the inclusion-exclusion terms add to the positive
+        // lists' own (which a single positive list does not need at all)
+        long long cost = 0;
         for (uint32_t T = 1; T < (1u << m_neg); ++T) {
           int mn = blen;
           uint32_t rest = neg;
@@ -344,14 +360,14 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 #pragma unroll
           for (int j = 0; j < J; ++j)
             if (ok && (((pos | tmask) >> j) & 1u) && sl != j)
-              ok = contains(g.col + rs[j], ulen[j], x);
+              ok = has_nb(g, v[j], g.col + rs[j], ulen[j], x);
           if (ok && (((pos | tmask) >> J) & 1u) && sl != J)
-            ok = contains(g.col + M.it_urs[i], M.it_urd[i], x);
+            ok = has_nb(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           if (direct) {
 #pragma unroll
             for (int j = 0; j < J; ++j)
-              if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], ulen[j], x);
-            if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + M.it_urs[i], M.it_urd[i], x);
+              if (ok && ((neg >> j) & 1u)) ok = !has_nb(g, v[j], g.col + rs[j], ulen[j], x);
+            if (ok && ((neg >> J) & 1u)) ok = !has_nb(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           }
         }
         local += ok ? sign : 0ll;
@@ -366,11 +382,11 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         bool ok = y < B;
         if (ok && use_src) ok = contains(srcset, slen, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((pos >> jj) & 1u)) ok = contains(g.col + rs[jj], ulen[jj], y);
-        if (ok && ((pos >> J) & 1u)) ok = contains(g.col + urs, urd, y);
+          if (ok && ((pos >> jj) & 1u)) ok = has_nb(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((pos >> J) & 1u)) ok = has_nb(g, u, g.col + urs, urd, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((neg >> jj) & 1u)) ok = !contains(g.col + rs[jj], ulen[jj], y);
-        if (ok && ((neg >> J) & 1u)) ok = !contains(g.col + urs, urd, y);
+          if (ok && ((neg >> jj) & 1u)) ok = !has_nb(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((neg >> J) & 1u)) ok = !has_nb(g, u, g.col + urs, urd, y);
         local -= ok ? 1ll : 0ll;
       }
     }
@@ -478,10 +494,10 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
       if (ok && use_src && slot != SRC_SLOT) ok = contains(srcset, src_len, x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((pos >> j) & 1u) && slot != j) ok = contains(g.col + rs[j], len[j], x);
+        if (ok && ((pos >> j) & 1u) && slot != j) ok = has_nb(g, v[j], g.col + rs[j], len[j], x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((neg >> j) & 1u)) ok = !contains(g.col + rs[j], len[j], x);
+        if (ok && ((neg >> j) & 1u)) ok = !has_nb(g, v[j], g.col + rs[j], len[j], x);
       const unsigned long long m = __ballot(ok);
       if (ok) out[nout + mbcnt(m)] = x;
       nout += __popcll(m);
@@ -1280,6 +1296,21 @@ __global__ void k_fill_u64(unsigned long long* p, long long n) {
   for (; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0ull;
 }
 
+// Neighbour bitmaps of vertices 0..n_hub-1 (rows cleared beforehand): one
+// workgroup per hub row at a time, each thread setting the bits of a strided
+// share of the hub's neighbours.
+__global__ void k_hub_bits(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                           uint32_t* bits, long long row_words, int32_t n_hub) {
+  for (int32_t v = blockIdx.x; v < n_hub; v += gridDim.x) {
+    uint32_t* row = bits + (long long)v * row_words;
+    const int32_t e = rowptr[v + 1];
+    for (int32_t i = rowptr[v] + (int32_t)threadIdx.x; i < e; i += (int32_t)blockDim.x) {
+      const int32_t x = col[i];
+      atomicOr(row + (x >> 5), 1u << (x & 31));
+    }
+  }
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------ host side
@@ -1398,6 +1429,85 @@ long long split_cap() {
     if (end && *end == '\0' && v >= 1 && v <= (1ll << 26)) return v;
   }
   return 1ll << 20;
+}
+
+// Vertices of at least this degree get a neighbour bitmap (GZ_HUB_MIN_DEG
+// overrides, >= 1).
+int hub_min_deg() {
+  const char* e = std::getenv("GZ_HUB_MIN_DEG");
+  if (e && *e) {
+    char* end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (end && *end == '\0' && v >= 1 && v <= INT32_MAX) return (int)v;
+  }
+  return 1024;
+}
+
+// Bytes all bitmaps of one graph may take (GZ_HUB_MAX_KB overrides, in KiB;
+// 0 switches the bitmaps off).
+long long hub_cap_bytes() {
+  const char* e = std::getenv("GZ_HUB_MAX_KB");
+  if (e && *e) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end && *end == '\0' && v >= 0 && v <= (1ll << 40)) return v << 10;
+  }
+  return 8ll << 30;
+}
+
+// The graph's hub bitmaps for the current settings, built on first use and
+// kept for the handle's life.  Hubs are the leading run of vertices of
+// degree >= hub_min_deg() (after the degree reindex: every such vertex),
+// cut to the byte cap.  When the allocation fails the graph simply has no
+// hubs: bitmaps only make probes cheaper, never change a result.
+gz_status graph_hubs(const gz_graph* g, hipStream_t st, HubMaps* out) {
+  const int md = hub_min_deg();
+  const long long cap = hub_cap_bytes();
+  std::lock_guard<std::mutex> lock(g->task_mu);
+  for (const HubMaps& hm : g->hub_cache)
+    if (hm.min_deg == md && hm.cap_bytes == cap) {
+      *out = hm;
+      return GZ_OK;
+    }
+  const HostGraph& h = g->host;
+  HubMaps hm;
+  hm.min_deg = md;
+  hm.cap_bytes = cap;
+  hm.row_words = ((long long)h.n + 31) / 32;
+  int32_t H = 0;
+  while (H < h.n && h.rowptr[H + 1] - h.rowptr[H] >= md) ++H;
+  const long long row_bytes = 4 * hm.row_words;
+  if (row_bytes > 0) H = (int32_t)std::min<long long>(H, cap / row_bytes);
+  if (H > 0) {
+    const long long words = (long long)H * hm.row_words;
+    const long long n64 = (words + 1) / 2;
+    void* p = nullptr;
+    if (hipMalloc(&p, 8 * n64) != hipSuccess) {
+      (void)hipGetLastError();
+      H = 0;
+    } else {
+      hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n64 + 255) / 256, 8192)),
+                         dim3(256), 0, st, (unsigned long long*)p, n64);
+      hipLaunchKernelGGL(dev::k_hub_bits, dim3((unsigned)std::min<int32_t>(H, 8192)), dim3(256), 0,
+                         st, g->d_rowptr, g->d_col, (uint32_t*)p, hm.row_words, H);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        (void)hipFree(p);
+        set_error(std::string("hub bitmap build: ") + hipGetErrorString(e));
+        return GZ_EDEVICE;
+      }
+      hm.bits = (uint32_t*)p;
+    }
+  }
+  hm.n_hub = H;
+  g->hub_cache.push_back(hm);
+  *out = hm;
+  return GZ_OK;
+}
+
+dev::Graph device_graph(const gz_graph* g, const HubMaps& hm) {
+  return dev::Graph{g->d_rowptr, g->d_col, g->d_lo, g->host.n, hm.bits, hm.n_hub, hm.row_words};
 }
 
 // One launch per loop depth over the recorded prefixes of that depth.
@@ -1805,11 +1915,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     set_error("operation counts exist only for the clique path over all roots");
     rc = GZ_ENOTSUP;
   }
-  // inclusion-exclusion in the last loop: only where it has negative lists
-  // and no restriction bound, the case where its positive list can be a
-  // whole hub row (its kernels hold more registers)
-  const bool ie = !instr && plan.k >= 3 && plan.lv[plan.k - 1].sub != 0 &&
-                  (plan.lv[plan.k - 1].bound < 0 || plan.ie_force);
+  // inclusion-exclusion in the last loop: wherever it has negative lists
+  const bool ie = !instr && plan.k >= 3 && plan.lv[plan.k - 1].sub != 0;
   // second phase of the generic path: long loop bases split into pieces
   const bool split = !rc && !use_clique && !instr && plan.k >= 4;
   const long long heavy_cap = split ? split_cap() : 0;
@@ -1818,6 +1925,9 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     set_error("device allocation of the split list failed");
     rc = GZ_ENOMEM;
   }
+  // neighbour bitmaps of the hubs for the generic path's probes
+  HubMaps hubs;
+  if (!rc && !use_clique) rc = graph_hubs(g, st, &hubs);
   void* heavy_scratch = nullptr;
   CliqueLists own_lists;
   const CliqueLists* lists = nullptr;
@@ -1838,7 +1948,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   if (!rc) {
     hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
                        dim3(256), 0, st, d_acc, n_acc);
-    dev::Graph dg{g->d_rowptr, g->d_col, g->d_lo, h.n};
+    const dev::Graph dg = device_graph(g, hubs);
     dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
                   split_min_len(), d_heavy, split ? heavy_cap : 0};
     dev::Out o{d_acc, d_acc + dev::ACC_HEAD};
@@ -2068,8 +2178,14 @@ gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
   if (!rc) {
     c->graphs.assign(graphs, graphs + n_graphs);
     c->scheds.assign(scheds, scheds + n_scheds);
-    std::vector<dev::Graph> gt;
-    for (const gz_graph* g : c->graphs) gt.push_back(dev::Graph{g->d_rowptr, g->d_col, g->d_lo, g->host.n});
+  }
+  std::vector<dev::Graph> gt;
+  for (int i = 0; i < n_graphs && !rc; ++i) {
+    HubMaps hm;
+    rc = graph_hubs(graphs[i], nullptr, &hm);
+    gt.push_back(device_graph(graphs[i], hm));
+  }
+  if (!rc) {
     std::vector<Plan> pt;
     for (const gz_schedule* s : c->scheds) pt.push_back(s->plan);
     if (hipStreamCreate(&c->stream) != hipSuccess ||
@@ -2170,6 +2286,9 @@ void free_graph_tasks(gz_graph* g) {
   g->task_cache.clear();
   free_clique_lists(&g->clique_all);
   g->clique_ready = false;
+  for (HubMaps& hm : g->hub_cache)
+    if (hm.bits) (void)hipFree(hm.bits);
+  g->hub_cache.clear();
 }
 
 }  // namespace gz

@@ -1,0 +1,157 @@
+"""GPU parity of the neighbour bitmaps of high-degree vertices.
+
+The generic path answers a membership probe into the list of a hub (one of
+the leading vertices of degree >= GZ_HUB_MIN_DEG after the degree reindex)
+with one bit of that hub's bitmap instead of a binary search.  The default
+threshold leaves the small test graphs without hubs, so these tests force it
+low (down to every vertex being a hub), cap the bitmaps' memory so that only
+part of the leading run gets rows, switch them off, and combine them with
+the two-phase split and forced inclusion-exclusion.  Counts must stay
+bit-exact against the oracle, in total and per root."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import patterns as P
+from paper_1911_12877_amd import gz, synth
+
+pytestmark = pytest.mark.gpu
+
+ENV = ("GZ_HUB_MIN_DEG", "GZ_HUB_MAX_KB", "GZ_SPLIT_MIN_LEN", "GZ_IE_FORCE")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gz.library()
+    yield
+    for k in ENV:
+        os.environ.pop(k, None)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class _env:
+    def __init__(self, **kv):
+        self.kv = kv
+
+    def __enter__(self):
+        for k, v in self.kv.items():
+            os.environ[k] = str(v)
+
+    def __exit__(self, *exc):
+        for k in self.kv:
+            os.environ.pop(k, None)
+
+
+PATS = [(nm, ind) for nm in ("triangle", "c4", "diamond", "tailed_triangle", "house", "k5e",
+                             "c5", "k4", "p4", "star4") for ind in (True, False)] + \
+    [("c6chord03", True), ("k6e", True)]
+
+
+@pytest.fixture(scope="module")
+def cl_case():
+    e = synth.chung_lu_edges(1500, 2.2, 10.0, 71, cap=False)
+    G = gz.load_edges(*e)
+    O = oracle.from_edge_tuple(e)
+    want = {(nm, ind): oracle.count(O, P.named(nm), ind) for nm, ind in PATS}
+    return G, O, want
+
+
+# (min degree, cap in KiB): every vertex, the hubs of degree >= 8 or 64,
+# and a cap that cuts the leading run after a few rows (1500-vertex rows
+# take 188 bytes)
+SETTINGS = [(1, None), (8, None), (64, None), (1, 1), ("1", 0)]
+
+
+@pytest.mark.parametrize("setting", SETTINGS)
+def test_hubs_match_oracle(cl_case, setting):
+    G, _, want = cl_case
+    md, cap = setting
+    kv = {"GZ_HUB_MIN_DEG": md}
+    if cap is not None:
+        kv["GZ_HUB_MAX_KB"] = cap
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        with _env(**kv):
+            _say("hubs", setting, nm, induced)
+            got = gz.count(G, s)
+        assert got == want[(nm, induced)], (nm, induced, setting)
+
+
+def test_hubs_with_split_and_inclusion_exclusion(cl_case):
+    G, _, want = cl_case
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        for kv in ({"GZ_HUB_MIN_DEG": 4, "GZ_SPLIT_MIN_LEN": 0},
+                   {"GZ_HUB_MIN_DEG": 4, "GZ_IE_FORCE": 1},
+                   {"GZ_HUB_MIN_DEG": 4, "GZ_IE_FORCE": 1, "GZ_SPLIT_MIN_LEN": 0}):
+            with _env(**kv):
+                got = gz.count(G, s)
+            assert got == want[(nm, induced)], (nm, induced, kv)
+
+
+@pytest.mark.parametrize("nm", ["c4", "house", "tailed_triangle", "k5e"])
+def test_hubs_per_root(nm):
+    e = synth.rmat_edges(10, 8, seed=72)
+    G = gz.load_edges(*e)
+    O = oracle.from_edge_tuple(e)
+    pat = P.named(nm)
+    s = gz.compile_pattern(pat, True)
+    roots = np.arange(O.n, dtype=np.int32)
+    total, want = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                               roots=roots, per_root=True)
+    with _env(GZ_HUB_MIN_DEG=16):
+        got = gz.count_roots(G, s, roots)
+    assert np.array_equal(got, want)
+    assert int(got.astype(object).sum()) == total
+
+
+def test_hubs_every_small_pattern():
+    graphs = [synth.er_edges(14, 0.45, 73), synth.rmat_edges(6, 6, seed=74),
+              synth.chung_lu_edges(40, 2.3, 6.0, 75, cap=False), synth.star_edges(9)]
+    for e in graphs:
+        G = gz.load_edges(*e)
+        O = oracle.from_edge_tuple(e)
+        for k in (3, 4, 5):
+            for pat in P.connected_patterns(k):
+                for induced in (True, False):
+                    want = oracle.count(O, pat, induced)
+                    s = gz.compile_pattern(pat, induced)
+                    with _env(GZ_HUB_MIN_DEG=1):
+                        assert gz.count(G, s) == want, (k, pat, induced)
+
+
+def test_hubs_without_reindex():
+    """Orientation off: ids keep the input order, so only the leading run of
+    high-degree ids gets rows (a star whose hub is vertex 0, then the rest)."""
+    a, b, n = synth.star_edges(60)
+    na, nb, _ = synth.er_edges(n, 0.08, 76)
+    e = (np.concatenate([a, na]).astype(np.int32), np.concatenate([b, nb]).astype(np.int32), n)
+    G = gz.load_edges(*e, flags=gz.GRAPH_NO_REINDEX)
+    O = oracle.from_edge_tuple(e, reindex_by_degree=False)
+    for nm in ("c4", "diamond", "tailed_triangle", "house"):
+        pat = P.named(nm)
+        want = oracle.count(O, pat, True)
+        with _env(GZ_HUB_MIN_DEG=5):
+            assert gz.count(G, gz.compile_pattern(pat, True)) == want, nm
+
+
+def test_census_with_hubs():
+    graphs = [synth.chung_lu_edges(300 + 100 * i, 2.3, 8.0, 77 + i, cap=True) for i in range(3)]
+    pats = [P.named(nm) for nm in ("c4", "diamond", "tailed_triangle", "house", "c5")]
+    Os = [oracle.from_edge_tuple(e) for e in graphs]
+    want = np.array([[oracle.count(O, p, True) for p in pats] for O in Os], dtype=np.uint64)
+    with _env(GZ_HUB_MIN_DEG=6):
+        Gs = [gz.load_edges(*e) for e in graphs]
+        c = gz.Census(Gs, [gz.compile_pattern(p, True) for p in pats])
+        got, _ = c.run()
+    assert np.array_equal(got, want)
