@@ -1,15 +1,33 @@
 #!/usr/bin/env python3
-"""Benchmark: exact k-clique counts (K4 and K5) on an R-MAT scale-20 graph.
+"""Benchmark: exact vertex-induced pattern counts on one MI355X.
 
-One step = one pass of the hot path over the resident graph: compile both
-patterns (automorphisms, distinct schedules, restrictions, analytic pick,
-lowering) and run both counting kernels.  Graph generation and preparation
-(normalisation + degree reindex + upload) happen once before timing and are
-reported separately, as the paper reports reindexing apart from mining.
+Default workload (``rmat22-induced``): the vertex-induced 4-cycle, diamond and
+tailed triangle on an R-MAT scale-22 graph (edge factor 16,
+(a,b,c,d) = (0.57,0.19,0.19,0.05), seed 3001; 4,194,304 vertices, 128.3 M
+neighbour entries), each with the analytic model's schedule, its symmetry
+restrictions and the degree orientation.  The count of a pattern decomposes
+exactly over the roots of its first loop (every instance has one restricted
+mapping), so the job is cut into S strided root slices (roots r with
+r = q mod S): one step counts every pattern of the workload over one slice,
+and S consecutive steps are one complete exact count of every pattern.
+Slices hold equal shares of every degree range, so their times agree to
+about 1%.  The full-count time of a pattern is the sum over one cycle of
+slices; it is reported whenever the timed steps cover a cycle.
 
-Prints one JSON line.  ``value`` is the intersect throughput of the whole
-step: algorithmic bytes of both patterns' bounded set operations (the same
-definition as gz_count_bytes) per second of wall time.
+Other workloads: ``rmat20-cliques`` (K4 and K5 on R-MAT scale 20, one full
+count of each per step) and ``er2000-triangles`` (triangles of
+G(2000, 0.008)).
+
+Graph generation and preparation (normalisation, degree reindex, upload)
+happen once before timing and are reported apart, as the paper reports its
+reindexing apart from mining.  Every step compiles its patterns (Aut,
+Algorithm 3, Algorithm 1 with Theorem 2, analytic pick, lowering) and runs the
+counts on the resident graph.
+
+Prints one JSON line.  ``value`` is exact instances counted per second of
+wall time over the timed steps.  ``roofline`` is the dominant kernel's rate
+against its bound; ``cpu_baseline`` is the oracle (plain C, one process per
+core, roots sharded) on a seeded root sample, in the same unit.
 """
 
 from __future__ import annotations
@@ -17,6 +35,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -33,15 +52,17 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4
 VALU_ISSUE_PEAK = 256 * 2.4e9
 
 WORKLOADS = {
-    "rmat20-cliques": dict(graph="rmat20", patterns=["k4", "k5"], induced=True,
+    # the house (and K5-e) of the same configuration are far beyond a
+    # benchmark run with this method: see the design notes
+    "rmat22-induced": dict(graph="rmat22", patterns=["c4", "diamond", "tailed_triangle"],
+                           induced=True, slices=128,
+                           desc="vertex-induced 4-cycle, diamond and tailed triangle, R-MAT "
+                                "scale 22, edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), "
+                                "seed 3001"),
+    "rmat20-cliques": dict(graph="rmat20", patterns=["k4", "k5"], induced=True, slices=1,
                            desc="K4 and K5 counts, R-MAT scale 20, edge factor 16, "
                                 "(a,b,c,d)=(0.57,0.19,0.19,0.05), seed 2001"),
-    # the tailed triangle, house and K5-e of the same configuration take from
-    # about 23 minutes to hours per full count, so only these two are timed
-    "rmat22-induced": dict(graph="rmat22", patterns=["c4", "diamond"], induced=True,
-                           desc="vertex-induced 4-cycle and diamond, R-MAT scale 22, "
-                                "edge factor 16, seed 3001"),
-    "er2000-triangles": dict(graph="er2000", patterns=["triangle"], induced=True,
+    "er2000-triangles": dict(graph="er2000", patterns=["triangle"], induced=True, slices=1,
                              desc="triangles, G(2000, 0.008), seed 1001"),
 }
 
@@ -58,60 +79,80 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from committed rocprof counter runs
-    (FETCH_SIZE + WRITE_SIZE, calibrated against a copy kernel), or None when
-    absent or taken on a different kernel source."""
+def load_counters(workload, pattern):
+    """Per-launch counter figures of `pattern`'s kernel from a committed
+    rocprof run (HBM bytes from FETCH_SIZE + WRITE_SIZE calibrated against a
+    copy kernel, VALU instructions), or {} when absent or taken on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
-        data = json.load(f)
-    rec = data.get(workload, {}).get(kernel)
+        rec = json.load(f).get(workload, {}).get(pattern)
     if not rec or rec.get("source_hash") != source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+        return {}
+    return rec
 
 
-def load_valu_insts(workload, kernel):
-    """VALU wave instructions per launch of `kernel` from a committed rocprof
-    counter run (SQ_INSTS_VALU), or None when absent or stale."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f).get(workload, {}).get(kernel)
-    if not rec or rec.get("source_hash") != source_hash():
-        return None
-    return rec.get("valu_insts_per_launch")
+# ------------------------------------------------------------ CPU baseline
+
+_CPU = {}  # prepared graph and schedules, inherited by forked workers
 
 
-def cpu_baseline(edges, pattern_names, induced, orders, bounds, target_s):
-    """The oracle (single-threaded C) on a seeded sample of roots; returns
-    (GB/s of algorithmic bytes, sample description)."""
-    import numpy as np
+def _cpu_shard(roots):
     import oracle
     from oracle import patterns as P
-    O = oracle.from_edge_tuple(edges)
+    O = _CPU["graph"]
+    t0 = time.perf_counter()
+    total = 0
+    for nm, order, bound in _CPU["scheds"]:
+        rel = [(bound[i], i) for i in range(len(bound)) if bound[i] >= 0]
+        total += oracle.count(O, P.named(nm), _CPU["induced"], order=order, relations=rel,
+                              roots=roots)
+    return total, time.perf_counter() - t0
+
+
+def cpu_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(edges, pattern_names, induced, orders, bounds, target_s, workers):
+    """The oracle (single-threaded C per process) on a seeded uniform sample
+    of roots, the same schedules and bounds as the GPU; the sample grows
+    until one core needs about target_s.  Then the same sample sharded
+    round-robin over `workers` processes.  Returns instances/s of both."""
+    import numpy as np
+    import oracle
+    _CPU["graph"] = oracle.from_edge_tuple(edges)
+    _CPU["scheds"] = list(zip(pattern_names, orders, bounds))
+    _CPU["induced"] = induced
+    n = _CPU["graph"].n
     rng = np.random.Generator(np.random.PCG64(12345))
+    perm = rng.permutation(n).astype(np.int32)
     n_roots = 256
     while True:
-        roots = np.sort(rng.choice(O.n, size=min(n_roots, O.n), replace=False)).astype(np.int32)
-        t0 = time.perf_counter()
-        for nm, order, bound in zip(pattern_names, orders, bounds):
-            rel = [(bound[i], i) for i in range(len(bound)) if bound[i] >= 0]
-            oracle.count(O, P.named(nm), induced, order=order, relations=rel, roots=roots)
-        dt = time.perf_counter() - t0
-        if dt >= target_s or n_roots >= O.n:
+        roots = np.sort(perm[:min(n_roots, n)])
+        count1, dt1 = _cpu_shard(roots)
+        if dt1 >= target_s or n_roots >= n:
             break
-        n_roots = int(min(O.n, n_roots * max(2.0, 1.2 * target_s / max(dt, 1e-3))))
-    nbytes = 0
-    for nm, order, bound in zip(pattern_names, orders, bounds):
-        b, _ = oracle.instrument(O, P.named(nm), induced, order, bound, roots=roots)
-        nbytes += b
-    desc = (f"{len(roots)} uniformly sampled roots (PCG64 seed 12345) of {O.n}, "
+        n_roots = int(min(n, n_roots * max(2.0, 1.2 * target_s / max(dt1, 1e-3))))
+    shards = [roots[w::workers] for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_shard, shards)
+    dtn = time.perf_counter() - t0
+    countn = sum(c for c, _ in res)
+    assert countn == count1, "sharded oracle disagrees with the single-process run"
+    _CPU.clear()
+    desc = (f"{len(roots)} uniformly sampled roots (PCG64 seed 12345) of {n}, "
             f"patterns {'+'.join(pattern_names)}, same schedules and bounds")
-    return nbytes / dt / 1e9, desc, dt
+    return count1 / dt1, dt1, countn / dtn, dtn, desc
+
+
+# --------------------------------------------------------- learned schedules
 
 
 def learned_vs_analytic(reps=2):
@@ -121,7 +162,6 @@ def learned_vs_analytic(reps=2):
     R-MAT scale 10 (edge factor 16, seed 8801) and Chung-Lu n = 4000
     (exponent 2.3, mean degree 10, seed 8802).  Best of `reps` timed runs per
     schedule; the counts must agree."""
-    import numpy as np
     from paper_1911_12877_amd import gz, learn, synth
     if not os.path.exists(learn.MODEL_PATH):
         return None
@@ -163,13 +203,18 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": 1 << 30, "launches": 5}), flush=True)
 
 
+# -------------------------------------------------------------------- main
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20-cliques", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22-induced", choices=sorted(WORKLOADS))
+    ap.add_argument("--slices", type=int, default=None,
+                    help="root slices per complete count (default: the workload's)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned vs analytic schedule comparison")
@@ -192,6 +237,7 @@ def main():
     from paper_1911_12877_amd import gz, motifs, synth
 
     wl = WORKLOADS[args.workload]
+    S = max(1, args.slices or wl["slices"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
 
@@ -209,102 +255,129 @@ def main():
     assert Gd.info() == G.info()
     del Gd
     info = G.info()
-    log(f"prepared graph n={info['n']} nnz={info['nnz']} max_deg={info['max_deg']} "
+    n = info["n"]
+    log(f"prepared graph n={n} nnz={info['nnz']} max_deg={info['max_deg']} "
         f"max_lo={info['max_lo_deg']} in {t_prep:.2f}s")
 
-    adjs = [motifs.named(nm) for nm in wl["patterns"]]
-    scheds = [gz.compile_pattern(a, wl["induced"]) for a in adjs]
-    infos = [s.info() for s in scheds]
-    alg_bytes = []
-    counts = []
-    for nm, s in zip(wl["patterns"], scheds):
-        if args.no_alg_bytes:
-            c, _ = gz.count_timed(G, s, stream=stream)
-            b = None
-        else:
-            b, c = gz.count_bytes(G, s, stream=stream)
-        alg_bytes.append(b)
-        counts.append(c)
-        log(f"{nm}: count={c} algorithmic bytes={b}")
+    pats = wl["patterns"]
+    adjs = [motifs.named(nm) for nm in pats]
+    infos = [gz.compile_pattern(a, wl["induced"]).info() for a in adjs]
+    all_roots = np.arange(n, dtype=np.int32)
+    slices = [all_roots[q::S] for q in range(S)]
 
-    def step():
-        ks = []
-        for nm, a in zip(wl["patterns"], adjs):
+    def step(i):
+        """Compile and count every pattern over slice i mod S (the whole
+        graph when S == 1): [(count, kernel ms)] per pattern."""
+        q = i % S
+        out = []
+        for a in adjs:
             s = gz.compile_pattern(a, wl["induced"])
-            c, ms = gz.count_timed(G, s, stream=stream)
-            ks.append((c, ms))
-        return ks
+            if S == 1:
+                out.append(gz.count_timed(G, s, stream=stream))
+            else:
+                out.append(gz.count_subset(G, s, slices[q], stream=stream))
+        return q, out
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        q, res = step(i)
+        log(f"warmup {i} (slice {q}): " + ", ".join(f"{nm} {ms:.1f} ms" for nm, (_, ms) in
+                                                      zip(pats, res)))
     torch.cuda.synchronize()
-    kern_ms = [0.0] * len(adjs)
+    recs = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        res = step()
-        for j, (c, ms) in enumerate(res):
-            assert c == counts[j], "count changed between runs"
-            kern_ms[j] += ms
-        log(f"step {i}: " + ", ".join(f"{nm} {ms:.2f} ms" for nm, (_, ms) in
-                                      zip(wl["patterns"], res)))
+    for i in range(args.warmup, args.warmup + args.steps):
+        q, res = step(i)
+        recs.append((q, res))
+        log(f"step {i - args.warmup} (slice {q}): " +
+            ", ".join(f"{nm} {c} in {ms:.1f} ms" for nm, (c, ms) in zip(pats, res)))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    avg_ms = [m / args.steps for m in kern_ms]
-    have_bytes = all(b is not None for b in alg_bytes)
-    value = sum(alg_bytes) / (ms_per_step / 1e3) / 1e9 if have_bytes else None
+    total_count = sum(c for _, res in recs for c, _ in res)
+    value = total_count / wall
 
-    dom = int(np.argmax(avg_ms))
+    # per pattern over the timed steps; complete counts when a cycle of
+    # slices was covered (the first S timed steps: S consecutive residues)
+    kern_ms = [sum(res[j][1] for _, res in recs) for j in range(len(pats))]
+    per_pattern = {}
+    for j, nm in enumerate(pats):
+        d = {"kernel_ms_per_step": round(kern_ms[j] / args.steps, 3),
+             "order": list(infos[j]["order"]), "bound": infos[j]["bound"]}
+        if args.steps >= S:
+            cyc = recs[:S]
+            d["count"] = sum(res[j][0] for _, res in cyc)
+            d["full_count_kernel_s"] = round(sum(res[j][1] for _, res in cyc) / 1e3, 3)
+        per_pattern[nm] = d
+
+    # dominant kernel: the pattern with the largest kernel time per step
+    dom = int(np.argmax(kern_ms))
+    dname = pats[dom]
     kdom = len(adjs[dom])
-    traffic = load_traffic(args.workload, wl["patterns"][dom])
+    ctr = load_counters(args.workload, dname)
+    sdom = gz.compile_pattern(adjs[dom], wl["induced"])
     ops = None
     try:  # clique schedules run on bit rows: an ALU-bound kernel pair
-        ops, _ = gz.count_ops(G, scheds[dom], stream=stream)
+        ops, _ = gz.count_ops(G, sdom, stream=stream) if S == 1 else (None, None)
     except gz.GzError:
         ops = None
+    q_dom = recs[0][0]
+    ms_dom = np.mean([res[dom][1] for q, res in recs if q == q_dom])
     if ops is not None:
-        achieved = ops / (avg_ms[dom] / 1e3) / 1e9
-        valu = load_valu_insts(args.workload, wl["patterns"][dom])
+        achieved = ops / (ms_dom / 1e3) / 1e9
+        valu = ctr.get("valu_insts_per_launch")
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_GOPS,
                     "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4),
-                    "traffic": traffic, "ops_per_launch": ops,
-                    "valu_issue_frac": (round(valu / (avg_ms[dom] / 1e3) / VALU_ISSUE_PEAK, 4)
+                    "traffic": ctr.get("bytes_per_launch"), "ops_per_launch": ops,
+                    "valu_issue_frac": (round(valu / (ms_dom / 1e3) / VALU_ISSUE_PEAK, 4)
                                         if valu else None),
                     "kernel": f"k_clique_wave<{kdom}> + k_clique_block<{kdom}>",
-                    "pattern": wl["patterns"][dom], "kernel_ms": round(avg_ms[dom], 4)}
+                    "pattern": dname, "kernel_ms": round(float(ms_dom), 4)}
     else:
-        achieved = alg_bytes[dom] / (avg_ms[dom] / 1e3) / 1e9 if have_bytes else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2) if have_bytes else None,
+        alg = None
+        if not args.no_alg_bytes:
+            # algorithmic bytes of the same launch: one instrumented pass
+            # over the dominant pattern's first timed slice
+            if S == 1:
+                alg, _ = gz.count_bytes(G, sdom, stream=stream)
+            else:
+                alg, _ = gz.count_bytes_subset(G, sdom, slices[q_dom], stream=stream)
+        achieved = alg / (ms_dom / 1e3) / 1e9 if alg is not None else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2) if alg else None,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4) if have_bytes else None,
-                    "traffic": traffic, "kernel": f"k_mine<{kdom}>",
-                    "pattern": wl["patterns"][dom], "kernel_ms": round(avg_ms[dom], 4)}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4) if alg else None,
+                    "traffic": ctr.get("bytes_per_launch"), "alg_bytes_per_launch": alg,
+                    "valu_issue_frac": (round(ctr["valu_insts_per_launch"] / (ms_dom / 1e3) /
+                                              VALU_ISSUE_PEAK, 4)
+                                        if ctr.get("valu_insts_per_launch") else None),
+                    "kernel": f"k_mine<{kdom}>", "pattern": dname,
+                    "launch": f"slice {q_dom} of {S}" if S > 1 else "full count",
+                    "kernel_ms": round(float(ms_dom), 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the oracle on a root sample ...")
-        gbs, desc, dt = cpu_baseline(edges, wl["patterns"], wl["induced"],
-                                     [i["order"] for i in infos], [i["bound"] for i in infos],
-                                     args.cpu_seconds)
-        cpu = {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": desc, "seconds": round(dt, 2)}
+        workers = cpu_cores()
+        log(f"timing the oracle on a root sample (1 core, then {workers}) ...")
+        v1, dt1, vn, dtn, desc = cpu_baseline(
+            edges, pats, wl["induced"], [i["order"] for i in infos], [i["bound"] for i in infos],
+            args.cpu_seconds, workers)
+        cpu = {"value": round(vn, 1), "unit": "instances/s", "cores": workers, "kind": "oracle",
+               "sample": desc, "seconds": round(dtn, 2),
+               "one_core": {"value": round(v1, 1), "seconds": round(dt1, 2)}}
 
     lva = None if args.no_learned else learned_vs_analytic()
 
     out = {
-        "metric": METRIC, "value": round(value, 2) if have_bytes else None, "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "graph": wl["desc"], "n": info["n"],
-                   "nnz": info["nnz"], "patterns": wl["patterns"],
-                   "induced": wl["induced"], "schedule": "analytic",
+        "metric": METRIC, "value": round(value, 1), "unit": "instances/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "graph": wl["desc"], "n": n,
+                   "nnz": info["nnz"], "patterns": pats, "induced": wl["induced"],
+                   "schedule": "analytic",
+                   "step": (f"every pattern over one of {S} strided root slices"
+                            if S > 1 else "one full count of every pattern"),
                    "parallelism": "single GPU"},
-        "counts": {nm: c for nm, c in zip(wl["patterns"], counts)},
-        "kernel_ms": {nm: round(m, 4) for nm, m in zip(wl["patterns"], avg_ms)},
-        "alg_bytes": {nm: b for nm, b in zip(wl["patterns"], alg_bytes)},
-        "counts_per_s": round(sum(counts) / (ms_per_step / 1e3), 1),
+        "patterns": per_pattern,
         "prep_s": round(t_prep, 3),
         "prep_device_s": round(t_prep_dev, 4),
         "roofline": roofline,

@@ -217,6 +217,22 @@ gz_status gz_count_roots(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_per_root);
 
 /*
+ * Count over a subset of the roots: the number of instances whose restricted
+ * mapping puts one of roots[0..n_roots) (prepared-graph ids, none listed
+ * twice) in the first loop, with the same kernels and launch shape as
+ * gz_count and, when kernel_ms is not NULL, their duration as in
+ * gz_count_timed.  Theorem 1 gives every instance exactly one restricted
+ * mapping, so the count decomposes exactly over roots: disjoint root sets
+ * covering all vertices sum to gz_count.  This is the unit a caller splits
+ * one count by (a share of the roots per device, or per step).  Errors as
+ * gz_count_roots.
+ */
+gz_status gz_count_subset(const gz_graph* g, const gz_schedule* s,
+                          const int32_t* roots, int64_t n_roots,
+                          void* hip_stream, uint64_t* out_count,
+                          float* kernel_ms);
+
+/*
  * Algorithmic bytes of one gz_count: over every evaluation of loops 1..k-1,
  * 4 bytes per element of each neighbour list the loop's set expression
  * reads (pattern-edge lists, plus pattern-non-edge lists when induced), cut
@@ -227,6 +243,16 @@ gz_status gz_count_roots(const gz_graph* g, const gz_schedule* s,
 gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_bytes,
                          uint64_t* out_count);
+
+/*
+ * gz_count_bytes over a subset of the roots (as in gz_count_subset): the
+ * algorithmic bytes of the evaluations reached from the listed roots, and
+ * their count.
+ */
+gz_status gz_count_bytes_subset(const gz_graph* g, const gz_schedule* s,
+                                const int32_t* roots, int64_t n_roots,
+                                void* hip_stream, uint64_t* out_bytes,
+                                uint64_t* out_count);
 
 /*
  * Clique schedules (K_k, 4 <= k <= 8) run on per-root bit rows: row p holds

@@ -497,6 +497,64 @@ gz_status gz_count_roots(const gz_graph* g, const gz_schedule* s, const int32_t*
                    nullptr, nullptr);
 }
 
+gz_status gz_count_subset(const gz_graph* g, const gz_schedule* s, const int32_t* roots,
+                          int64_t n_roots, void* hip_stream, uint64_t* out_count,
+                          float* kernel_ms) {
+  gz_status rc = check_run(g, s);
+  if (rc) return rc;
+  if (!out_count || n_roots < 0 || (n_roots > 0 && !roots)) {
+    set_error(out_count ? "bad root list" : "NULL output pointer");
+    return GZ_EINVAL;
+  }
+  for (int64_t i = 0; i < n_roots; ++i)
+    if (roots[i] < 0 || roots[i] >= g->host.n) {
+      set_error("root id out of range");
+      return GZ_EINVAL;
+    }
+  *out_count = 0;
+  if (kernel_ms) *kernel_ms = 0.0f;
+  if (n_roots == 0) return GZ_OK;
+  unsigned __int128 total = 0;
+  rc = run_count(g, s, (hipStream_t)hip_stream, roots, n_roots, nullptr, false, &total, nullptr,
+                 kernel_ms);
+  if (rc) return rc;
+  if (total >> 64) {
+    set_error("count does not fit in 64 bits");
+    return GZ_EOVERFLOW;
+  }
+  *out_count = (uint64_t)total;
+  return GZ_OK;
+}
+
+gz_status gz_count_bytes_subset(const gz_graph* g, const gz_schedule* s, const int32_t* roots,
+                                int64_t n_roots, void* hip_stream, uint64_t* out_bytes,
+                                uint64_t* out_count) {
+  gz_status rc = check_run(g, s);
+  if (rc) return rc;
+  if (n_roots < 0 || (n_roots > 0 && !roots)) {
+    set_error("bad root list");
+    return GZ_EINVAL;
+  }
+  for (int64_t i = 0; i < n_roots; ++i)
+    if (roots[i] < 0 || roots[i] >= g->host.n) {
+      set_error("root id out of range");
+      return GZ_EINVAL;
+    }
+  unsigned __int128 total = 0, bytes = 0;
+  if (n_roots > 0) {
+    rc = run_count(g, s, (hipStream_t)hip_stream, roots, n_roots, nullptr, true, &total, &bytes,
+                   nullptr);
+    if (rc) return rc;
+  }
+  if ((total >> 64) || (bytes >> 64)) {
+    set_error("count or byte total does not fit in 64 bits");
+    return GZ_EOVERFLOW;
+  }
+  if (out_bytes) *out_bytes = (uint64_t)bytes;
+  if (out_count) *out_count = (uint64_t)total;
+  return GZ_OK;
+}
+
 gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                          uint64_t* out_bytes, uint64_t* out_count) {
   gz_status rc = check_run(g, s);

@@ -143,9 +143,10 @@ __device__ __forceinline__ bool contains(P a, int len, int32_t x) {
 // Every caller probes with an x below the cut's bound (x comes from a list
 // cut at the same bound), so membership in the cut is membership in N(v):
 // one bit of v's bitmap when v is a hub, else a binary search of the cut.
+template <bool HUB>
 __device__ __forceinline__ bool has_nb(const Graph& g, int32_t v, const int32_t* row, int len,
                                        int32_t x) {
-  if (v < g.n_hub)
+  if (HUB && v < g.n_hub)
     return (g.hub[(long long)v * g.hub_words + (x >> 5)] >> (x & 31)) & 1u;
   return contains(row, len, x);
 }
@@ -189,7 +190,7 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
 // Every (item, term, element) pair is one lane's work; an item's terms are
 // all counted within this call, so the signed partial sums of the call
 // total the (non-negative) count of its items.
-template <int K, bool INSTR, bool IE>
+template <int K, bool INSTR, bool IE, bool HUB = true>
 __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                            const int32_t (&v)[K], const int32_t (&rs)[K],
                            const int32_t (&rd)[K], uint32_t complete,
@@ -360,14 +361,14 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 #pragma unroll
           for (int j = 0; j < J; ++j)
             if (ok && (((pos | tmask) >> j) & 1u) && sl != j)
-              ok = has_nb(g, v[j], g.col + rs[j], ulen[j], x);
+              ok = has_nb<HUB>(g, v[j], g.col + rs[j], ulen[j], x);
           if (ok && (((pos | tmask) >> J) & 1u) && sl != J)
-            ok = has_nb(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
+            ok = has_nb<HUB>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           if (direct) {
 #pragma unroll
             for (int j = 0; j < J; ++j)
-              if (ok && ((neg >> j) & 1u)) ok = !has_nb(g, v[j], g.col + rs[j], ulen[j], x);
-            if (ok && ((neg >> J) & 1u)) ok = !has_nb(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
+              if (ok && ((neg >> j) & 1u)) ok = !has_nb<HUB>(g, v[j], g.col + rs[j], ulen[j], x);
+            if (ok && ((neg >> J) & 1u)) ok = !has_nb<HUB>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           }
         }
         local += ok ? sign : 0ll;
@@ -382,11 +383,11 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         bool ok = y < B;
         if (ok && use_src) ok = contains(srcset, slen, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((pos >> jj) & 1u)) ok = has_nb(g, v[jj], g.col + rs[jj], ulen[jj], y);
-        if (ok && ((pos >> J) & 1u)) ok = has_nb(g, u, g.col + urs, urd, y);
+          if (ok && ((pos >> jj) & 1u)) ok = has_nb<HUB>(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((pos >> J) & 1u)) ok = has_nb<HUB>(g, u, g.col + urs, urd, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((neg >> jj) & 1u)) ok = !has_nb(g, v[jj], g.col + rs[jj], ulen[jj], y);
-        if (ok && ((neg >> J) & 1u)) ok = !has_nb(g, u, g.col + urs, urd, y);
+          if (ok && ((neg >> jj) & 1u)) ok = !has_nb<HUB>(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((neg >> J) & 1u)) ok = !has_nb<HUB>(g, u, g.col + urs, urd, y);
         local -= ok ? 1ll : 0ll;
       }
     }
@@ -417,7 +418,7 @@ struct Split {
   int32_t r;                     // current root slot
 };
 
-template <int K, int I, bool INSTR, bool IE>
+template <int K, int I, bool INSTR, bool IE, bool HUB = true>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
                           uint32_t complete, int rank_prev, Acc& acc, const Split& sp,
@@ -494,10 +495,10 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
       if (ok && use_src && slot != SRC_SLOT) ok = contains(srcset, src_len, x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((pos >> j) & 1u) && slot != j) ok = has_nb(g, v[j], g.col + rs[j], len[j], x);
+        if (ok && ((pos >> j) & 1u) && slot != j) ok = has_nb<HUB>(g, v[j], g.col + rs[j], len[j], x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((neg >> j) & 1u)) ok = !has_nb(g, v[j], g.col + rs[j], len[j], x);
+        if (ok && ((neg >> j) & 1u)) ok = !has_nb<HUB>(g, v[j], g.col + rs[j], len[j], x);
       const unsigned long long m = __ballot(ok);
       if (ok) out[nout + mbcnt(m)] = x;
       nout += __popcll(m);
@@ -505,13 +506,13 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     if (lane == 0) M.set_len[I - 2] = nout;
     wave_sync();
     if constexpr (I == K - 2) {
-      last_level<K, INSTR, IE>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
+      last_level<K, INSTR, IE, HUB>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
     } else {
       for (int t = 0; t < nout; ++t) {
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR, IE>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
+        mat_level<K, I + 1, INSTR, IE, HUB>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
       }
     }
     cum += nout;
@@ -1171,7 +1172,8 @@ __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const 
 // pair through an exclusive prefix over the pairs' task counts, then a
 // first-loop task of that pair through the graph's own task prefix; the
 // task runs the same loops as k_mine and its count is added to the pair's
-// 128-bit accumulator.
+// 128-bit accumulator.  The 6-7-vertex kernel probes lists by binary search
+// only: the hub bitmap test would make it spill registers.
 
 struct CensusPair {
   const int64_t* prefix;  // first-loop task prefix of the pair's graph (n + 1)
@@ -1212,7 +1214,7 @@ union CensusWaveMem<7> {
   WaveMem<7> m7;
 };
 
-template <int K>
+template <int K, bool HUB>
 __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
                             const CensusPair& pr, long long local, Acc& acc) {
   const int lane = lane_id();
@@ -1236,14 +1238,15 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
   if constexpr (K == 2) {
     if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
   } else if constexpr (K == 3) {
-    last_level<K, false, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin, begin, acc);
+    last_level<K, false, false, HUB>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin,
+                                     begin, acc);
   } else {
     for (int32_t i = begin; i < end; ++i) {
       v[1] = uni(g.col[rs0 + i]);
       rs[1] = uni(g.rowptr[v[1]]);
       rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
       const Split none{nullptr, nullptr, 0, INF, 0};
-      mat_level<K, 2, false, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
+      mat_level<K, 2, false, false, HUB>(g, plan, M, v, rs, rd, 0u, i, acc, none);
     }
   }
 }
@@ -1275,14 +1278,14 @@ __global__ __launch_bounds__(BLOCK) void k_census(CensusArgs A) {
       Acc acc{0ull, 0ull};
       if constexpr (KMAX == 5) {
         switch (plan.k) {
-          case 2: census_task<2>(g, plan, M.m2, pr, local, acc); break;
-          case 3: census_task<3>(g, plan, M.m3, pr, local, acc); break;
-          case 4: census_task<4>(g, plan, M.m4, pr, local, acc); break;
-          default: census_task<5>(g, plan, M.m5, pr, local, acc); break;
+          case 2: census_task<2, true>(g, plan, M.m2, pr, local, acc); break;
+          case 3: census_task<3, true>(g, plan, M.m3, pr, local, acc); break;
+          case 4: census_task<4, true>(g, plan, M.m4, pr, local, acc); break;
+          default: census_task<5, true>(g, plan, M.m5, pr, local, acc); break;
         }
       } else {
-        if (plan.k == 6) census_task<6>(g, plan, M.m6, pr, local, acc);
-        else census_task<7>(g, plan, M.m7, pr, local, acc);
+        if (plan.k == 6) census_task<6, false>(g, plan, M.m6, pr, local, acc);
+        else census_task<7, false>(g, plan, M.m7, pr, local, acc);
       }
       unsigned long long l, h;
       wave_sum_u128(acc.cnt, &l, &h);
@@ -1874,7 +1877,8 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
   const int chunk = chunk_for(plan.k);
-  const bool pr = roots != nullptr;
+  const bool pr = roots != nullptr;         // a root list is given
+  const bool out_pr = per_root != nullptr;  // per-root counts are wanted
 
   DevTasks tasks;
   int64_t* own_prefix = nullptr;
@@ -1903,7 +1907,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   }
 
   unsigned long long* d_acc = nullptr;
-  const long long n_acc = dev::ACC_HEAD + (pr ? nr : 0);
+  const long long n_acc = dev::ACC_HEAD + (out_pr ? nr : 0);
   gz_status rc = GZ_OK;
   if (hipMalloc(&d_acc, sizeof(unsigned long long) * n_acc) != hipSuccess) {
     set_error("device allocation of the accumulators failed");
@@ -1963,18 +1967,18 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
     if (!rc && tasks.n_tasks > 0) {
       if (use_clique) {
-        rc = pr ? launch_clique<true, false>(plan.k, dg, *lists, o, st)
+        rc = out_pr ? launch_clique<true, false>(plan.k, dg, *lists, o, st)
                 : (clique_ops ? launch_clique<false, true>(plan.k, dg, *lists, o, st)
                               : launch_clique<false, false>(plan.k, dg, *lists, o, st));
-      } else if (pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
-      else if (pr) rc = ie ? launch_by_k<true, false, true>(plan.k, dg, plan, dt, o, st)
+      } else if (out_pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
+      else if (out_pr) rc = ie ? launch_by_k<true, false, true>(plan.k, dg, plan, dt, o, st)
                            : launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);
       else if (instr) rc = launch_by_k<false, true>(plan.k, dg, plan, dt, o, st);
       else rc = ie ? launch_by_k<false, false, true>(plan.k, dg, plan, dt, o, st)
                    : launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
     }
     if (!rc && split && tasks.n_tasks > 0)
-      rc = run_heavy(dg, plan, pr, d_heavy, heavy_cap, d_acc + 6, o, st, &heavy_scratch, ie);
+      rc = run_heavy(dg, plan, out_pr, d_heavy, heavy_cap, d_acc + 6, o, st, &heavy_scratch, ie);
     if (kernel_ms && !rc) {
       if (hipEventRecord(ev1, st) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess ||
           hipEventElapsedTime(kernel_ms, ev0, ev1) != hipSuccess) {
@@ -2015,7 +2019,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     }
     *bytes = b;
   }
-  if (pr) {
+  if (out_pr) {
     if (hacc[5]) {
       set_error("a per-root count does not fit in 64 bits");
       return GZ_EOVERFLOW;

@@ -70,6 +70,8 @@ def _load():
         "gz_count": [P, P, P, P],
         "gz_count_timed": [P, P, P, P, P],
         "gz_count_roots": [P, P, P, i64, P, P],
+        "gz_count_subset": [P, P, P, i64, P, P, P],
+        "gz_count_bytes_subset": [P, P, P, i64, P, P, P],
         "gz_count_bytes": [P, P, P, P, P],
         "gz_count_ops": [P, P, P, P, P],
         "gz_census_create": [P, i32, P, i32, P],
@@ -342,11 +344,32 @@ def count_roots(g: Graph, s: Schedule, roots, stream=None):
     return out[:r.shape[0]]
 
 
+def count_subset(g: Graph, s: Schedule, roots, stream=None):
+    """gz_count_subset -> (count over the listed roots, kernel milliseconds)."""
+    r = _np(roots, np.int32)
+    out = ctypes.c_uint64()
+    ms = ctypes.c_float()
+    _check(_load().gz_count_subset(g.handle, s.handle, r.ctypes.data if r.size else None,
+                                   r.shape[0], _stream_ptr(stream), ctypes.byref(out),
+                                   ctypes.byref(ms)))
+    return int(out.value), float(ms.value)
+
+
 def count_bytes(g: Graph, s: Schedule, stream=None):
     """(algorithmic bytes, count) of one instrumented pass."""
     b, c = ctypes.c_uint64(), ctypes.c_uint64()
     _check(_load().gz_count_bytes(g.handle, s.handle, _stream_ptr(stream), ctypes.byref(b),
                                   ctypes.byref(c)))
+    return int(b.value), int(c.value)
+
+
+def count_bytes_subset(g: Graph, s: Schedule, roots, stream=None):
+    """(algorithmic bytes, count) of one instrumented pass over the listed roots."""
+    r = _np(roots, np.int32)
+    b, c = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_load().gz_count_bytes_subset(g.handle, s.handle, r.ctypes.data if r.size else None,
+                                         r.shape[0], _stream_ptr(stream), ctypes.byref(b),
+                                         ctypes.byref(c)))
     return int(b.value), int(c.value)
 
 

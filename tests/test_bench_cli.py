@@ -22,3 +22,19 @@ def test_workloads_name_known_graphs():
     for name, wl in bench.WORKLOADS.items():
         assert wl["graph"] in synth.CONFIGS, name
         assert wl["patterns"], name
+
+
+def test_cpu_baseline_sharded_oracle_agrees():
+    """The benchmark's CPU leg runs the oracle once on one core and again
+    sharded round-robin over worker processes; both see the same sample."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1911_12877_amd import synth
+    from oracle import patterns as P
+    e = synth.config_graph("er2000")
+    order = P.pick_schedule(P.named("triangle"), True)[0]
+    bound = list(P.reduced_bounds(P.named("triangle"), order))
+    v1, dt1, vn, dtn, desc = bench.cpu_baseline(e, ["triangle"], True, [order], [bound],
+                                                target_s=0.05, workers=2)
+    assert v1 > 0 and vn > 0 and dt1 > 0 and dtn > 0
+    assert "roots" in desc
