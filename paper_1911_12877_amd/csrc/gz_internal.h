@@ -55,6 +55,15 @@ struct Plan {
   int32_t induced;
   Level lv[kMaxK];
   int32_t ie_force = 0;  // last loop: inclusion-exclusion for every item (tests)
+  // last loop: items whose walk reaches long_min elements are counted by the
+  // whole wave, merging probe lists at most merge_ratio / 8 times the walk's
+  // length through an LDS window (set per count call)
+  int32_t long_min = 1 << 30;
+  int32_t merge_ratio = 4;
+  // last loop: an item takes inclusion-exclusion when its unit cost (walked
+  // elements times probes per element) is below ie_ratio / 8 of the direct
+  // evaluation's
+  int32_t ie_ratio = 12;
 };
 
 // ---------------------------------------------------------------- patterns

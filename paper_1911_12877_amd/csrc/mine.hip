@@ -42,6 +42,11 @@ constexpr int BLOCK = 256;
 constexpr int WPB = BLOCK / WAVE;     // waves per workgroup
 constexpr int32_t INF = 0x7fffffff;
 constexpr int SRC_SLOT = 8;
+// walk elements per step of a whole-wave walk: four loads in flight per lane
+// for 3- and 4-vertex patterns, fewer for larger ones (registers)
+constexpr int WALK_TILE = 4 * WAVE;
+template <int K>
+constexpr int walk_tile() { return K <= 4 ? WALK_TILE : (K <= 5 ? 2 * WAVE : WAVE); }
 
 struct Graph {
   const int32_t* __restrict__ rowptr;
@@ -93,6 +98,12 @@ struct WaveMem {
   int32_t it_urs[WAVE];
   int32_t it_urd[WAVE];
   int32_t it_ie[WAVE];
+  int32_t win[WALK_TILE];  // a window of a list being merged (long last-loop walks)
+  // the lists of the long walk being counted: start in col, bounded length
+  // and owner vertex, by list index (see Lists)
+  int32_t ls_start[K];
+  int32_t ls_len[K];
+  int32_t ls_owner[K];
 };
 
 struct Acc {
@@ -142,11 +153,12 @@ __device__ __forceinline__ bool contains(P a, int len, int32_t x) {
 // Is x in the list of v, given as its row cut to the first len entries?
 // Every caller probes with an x below the cut's bound (x comes from a list
 // cut at the same bound), so membership in the cut is membership in N(v):
-// one bit of v's bitmap when v is a hub, else a binary search of the cut.
-template <bool HUB>
+// one bit of v's bitmap when v is a hub (in the kernels for large graphs,
+// BIG), else a binary search of the cut.
+template <bool BIG>
 __device__ __forceinline__ bool has_nb(const Graph& g, int32_t v, const int32_t* row, int len,
                                        int32_t x) {
-  if (HUB && v < g.n_hub)
+  if (BIG && v < g.n_hub)
     return (g.hub[(long long)v * g.hub_words + (x >> 5)] >> (x & 31)) & 1u;
   return contains(row, len, x);
 }
@@ -174,6 +186,92 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
 
 // ------------------------------------------------------------ last loop
 
+// How many x of the sorted walk W[0..lw) lie in every list of `pos`, in no
+// list of `neg`, in the materialised set src[0..src_len) when src_len >= 0,
+// and differ from the owners of the lists in `exm` - the whole wave taking
+// walk_tile<K>() consecutive elements of W at a time (coalesced, up to
+// four loads in flight per lane).  The lists are those of one last-loop evaluation, held
+// in the wave's LDS (ls_start, ls_len, ls_owner: index j < K - 2 is loop
+// j's row, K - 2 the item's own row, each cut to its bounded length).  A
+// probe list at most ratio8 / 8 times as long as the walk is merged: the
+// wave streams it forward a tile of entries at a time through an LDS window
+// alongside the walk, each window holding the entries up to the tile's
+// largest element, and every lane binary-searches the window; longer lists
+// (a hub's row beside a short walk) are probed per element, by bitmap or
+// binary search.  The result is wave-uniform.
+template <int K, bool BIG>
+__device__ long long wave_walk(const Graph& g, WaveMem<K>& M, const int32_t* W, int lw,
+                               uint32_t pos, uint32_t neg, const int32_t* src, int src_len,
+                               uint32_t exm, int ratio8) {
+  constexpr int TILE = walk_tile<K>();
+  constexpr int U = TILE / WAVE;
+  const int lane = lane_id();
+  uint32_t mer = 0;
+  int pc[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    pc[j] = 0;
+    if ((((pos | neg) >> j) & 1u) && 8ll * M.ls_len[j] <= (long long)ratio8 * lw) mer |= 1u << j;
+  }
+  long long cnt = 0;
+  for (int t0 = 0; t0 < lw; t0 += TILE) {
+    int32_t x[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = t0 + u * WAVE + lane;
+      ok[u] = idx < lw;
+      x[u] = ok[u] ? W[idx] : INF;
+    }
+    const int32_t xmax = W[min(t0 + TILE, lw) - 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if ((exm >> j) & 1u) ok[u] = ok[u] && x[u] != M.ls_owner[j];
+      if (ok[u] && src_len >= 0) ok[u] = contains(src, src_len, x[u]);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (!(((pos | neg) >> j) & 1u)) continue;
+      const int32_t* P = g.col + M.ls_start[j];
+      const int plen = M.ls_len[j];
+      const bool want = ((pos >> j) & 1u) != 0;
+      bool in[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) in[u] = false;
+      if ((mer >> j) & 1u) {
+        for (;;) {
+          int c = 0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = pc[j] + u * WAVE + lane;
+            const int32_t y = q < plen ? P[q] : INF;
+            c += __popcll(__ballot(y <= xmax));
+            M.win[u * WAVE + lane] = y;
+          }
+          wave_sync();
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (ok[u] && !in[u]) in[u] = contains(M.win, c, x[u]);
+          wave_sync();
+          pc[j] += c;
+          if (c < TILE) break;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (ok[u]) in[u] = has_nb<BIG>(g, M.ls_owner[j], P, plen, x[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok[u] = ok[u] && (in[u] == want);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cnt += __popcll(__ballot(ok[u]));
+  }
+  return cnt;
+}
+
 // Count of the last loop for the items of one chunk of loop K-2.
 //
 // Each item's candidates are x < B in every positive list (the loop's
@@ -184,13 +282,16 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
 //  * inclusion-exclusion over the negative lists N_1..N_m:
 //      sum over T of (-1)^|T| |(all positive lists) and (N_j, j in T)|,
 //    each term walked from its own shortest bounded list, less the excl
-//    vertices that pass every test.  An item takes it when the sum of its
-//    terms' walk lengths is below the direct one: a hub's long positive list
-//    is then never walked when its negative lists are short.
-// Every (item, term, element) pair is one lane's work; an item's terms are
-// all counted within this call, so the signed partial sums of the call
-// total the (non-negative) count of its items.
-template <int K, bool INSTR, bool IE, bool HUB = true>
+//    vertices that pass every test.  An item takes it when its unit cost
+//    (walked elements times the lists probed per element) is lower: a
+//    hub's long positive list is then never walked when its negative lists
+//    are short.
+// Items whose walk is short share the wave: every (item, term, element)
+// pair is one lane's work.  Items with a long walk are counted one at a time
+// by the whole wave (wave_walk).  An item's terms are all counted within this
+// call, so the signed partial sums of the call total the (non-negative)
+// count of its items.
+template <int K, bool INSTR, bool IE, bool BIG>
 __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                            const int32_t (&v)[K], const int32_t (&rs)[K],
                            const int32_t (&rd)[K], uint32_t complete,
@@ -233,6 +334,7 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 #pragma unroll
     for (int j = 0; j < K; ++j) len[j] = 0;
     bool ie = false;
+    long long ie_walk = 0;
     if (valid) {
       if (use_src) {
         slen = (L.src == J && item_bound) ? t : lower_bound(srcset, src_full, B);
@@ -269,15 +371,19 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
             b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
         if ((all >> J) & 1u) b += 4ull * (unsigned)bounded_len(g, u, urs, urd, B, item_bound) + 8ull;
         acc.bytes += b;
-      } else if (IE && m_neg > 0 && (plan.ie_force || blen > IE_MIN)) {
+      } else if (IE && m_neg > 0 && (plan.ie_force || blen > IE_MIN || BIG)) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
           if ((neg >> j) & 1u)
             len[j] = item_bound ? lower_bound(g.col + rs[j], rd[j], B) : ulen[j];
         if ((neg >> J) & 1u) len[J] = bounded_len(g, u, urs, urd, B, item_bound);
-        // walk length the inclusion-exclusion terms add to the positive
-        // lists' own (which a single positive list does not need at all)
-        long long cost = 0;
+        // unit costs (one per walked element and per probe of it): direct
+        // walks the base and probes every other list; inclusion-exclusion
+        // walks the base with the positive lists only (not at all when it
+        // is the only one) and each term's shortest list with the term's
+        // lists as positive ones
+        long long& cost = ie_walk;
+        long long ie_cost = n_pos > 1 ? (long long)blen * n_pos : 0;
         for (uint32_t T = 1; T < (1u << m_neg); ++T) {
           int mn = blen;
           uint32_t rest = neg;
@@ -287,13 +393,20 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
             if ((T >> q) & 1u) mn = min(mn, len[j]);
           }
           cost += mn;
+          ie_cost += (long long)mn * (n_pos + __popc(T));
         }
-        ie = plan.ie_force || 2 * cost < (long long)blen;
+        const long long direct_cost = (long long)blen * (n_pos + m_neg);
+        ie = plan.ie_force ||
+             (blen > IE_MIN && 8 * ie_cost < (long long)plan.ie_ratio * direct_cost);
       }
     } else {
       blen = 0;
     }
-    const bool any_ie = IE && __ballot(ie) != 0ull;
+    // items with a long walk are counted by the whole wave below, 64
+    // consecutive elements at a time; the rest share the wave pair by pair
+    const long long walk = ie ? (n_pos > 1 ? blen : 0) + ie_walk : blen;
+    const bool lng = BIG && !INSTR && valid && walk >= plan.long_min;
+    const bool any_ie = IE && __ballot(ie && !lng) != 0ull;
     const uint32_t n_terms = any_ie ? (1u << m_neg) : 1u;
     M.it_u[lane] = u;
     M.it_srclen[lane] = slen;
@@ -312,7 +425,9 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         }
       }
       int elen = 0, eslot = slot, estart = bstart;
-      if (!ie) {
+      if (lng) {
+        elen = 0;
+      } else if (!ie) {
         elen = (T == 0) ? blen : 0;
       } else if (T == 0) {
         if (n_pos == 1) local += blen;  // a single bounded list: its length
@@ -361,19 +476,83 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
 #pragma unroll
           for (int j = 0; j < J; ++j)
             if (ok && (((pos | tmask) >> j) & 1u) && sl != j)
-              ok = has_nb<HUB>(g, v[j], g.col + rs[j], ulen[j], x);
+              ok = has_nb<BIG>(g, v[j], g.col + rs[j], ulen[j], x);
           if (ok && (((pos | tmask) >> J) & 1u) && sl != J)
-            ok = has_nb<HUB>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
+            ok = has_nb<BIG>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           if (direct) {
 #pragma unroll
             for (int j = 0; j < J; ++j)
-              if (ok && ((neg >> j) & 1u)) ok = !has_nb<HUB>(g, v[j], g.col + rs[j], ulen[j], x);
-            if (ok && ((neg >> J) & 1u)) ok = !has_nb<HUB>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
+              if (ok && ((neg >> j) & 1u)) ok = !has_nb<BIG>(g, v[j], g.col + rs[j], ulen[j], x);
+            if (ok && ((neg >> J) & 1u)) ok = !has_nb<BIG>(g, uu, g.col + M.it_urs[i], M.it_urd[i], x);
           }
         }
         local += ok ? sign : 0ll;
       }
       wave_sync();
+    }
+    // long walks: one item at a time over the whole wave
+    if constexpr (BIG) {
+      for (unsigned long long lm = __ballot(lng); lm; lm &= lm - 1) {
+        const int i = __ffsll((long long)lm) - 1;
+        const int32_t ui = uni(__shfl(u, i, WAVE)), ursi = uni(__shfl(urs, i, WAVE));
+        const int sloti = uni(__shfl(slot, i, WAVE)), bleni = uni(__shfl(blen, i, WAVE));
+        const int bstarti = uni(__shfl(bstart, i, WAVE)), sleni = uni(__shfl(slen, i, WAVE));
+        const bool iei = uni(__shfl(ie ? 1 : 0, i, WAVE)) != 0;
+        // the item's lists, into the wave's LDS
+        {
+          // bounded lengths: the item's own, from its lane
+          int32_t st = 0, ow = 0, ln = 0;
+#pragma unroll
+          for (int j = 0; j <= J; ++j) {
+            const int32_t lj = __shfl(len[j], i, WAVE);
+            if (lane == j) {
+              st = (j == J) ? ursi : rs[j];
+              ow = (j == J) ? ui : v[j];
+              ln = lj;
+            }
+          }
+          if (lane < K) {
+            M.ls_start[lane] = st;
+            M.ls_len[lane] = ln;
+            M.ls_owner[lane] = ow;
+          }
+        }
+        wave_sync();
+        const uint32_t nt = iei ? (1u << m_neg) : 1u;
+        for (uint32_t T = 0; T < nt; ++T) {
+          uint32_t tmask = 0;
+          {
+            uint32_t rest = neg;
+            for (int q = 0; q < m_neg; ++q) {
+              const int j = __ffs(rest) - 1;
+              rest &= rest - 1;
+              if ((T >> q) & 1u) tmask |= 1u << j;
+            }
+          }
+          // the term's walk: the base list, or a shorter list of the term
+          int es = sloti, el = bleni;
+          if (iei && T > 0) {
+            for (int j = 0; j <= J; ++j)
+              if (((tmask >> j) & 1u) && M.ls_len[j] < el) {
+                el = M.ls_len[j];
+                es = j;
+              }
+          }
+          long long c;
+          if (iei && T == 0 && n_pos == 1) {
+            c = bleni;  // a single bounded list: its length
+          } else {
+            const int32_t* Wp = (es == SRC_SLOT) ? srcset
+                                : g.col + (es == sloti ? bstarti : M.ls_start[es]);
+            const uint32_t pm = (pos | tmask) & ~(es == SRC_SLOT ? 0u : (1u << es));
+            c = wave_walk<K, BIG>(g, M, Wp, el, pm, iei ? 0u : neg, srcset,
+                                  (use_src && es != SRC_SLOT) ? sleni : -1,
+                                  iei ? 0u : (uint32_t)L.excl, plan.merge_ratio);
+          }
+          if (lane == 0) local += (__popc(T) & 1) ? -c : c;
+        }
+        wave_sync();  // the item's lists stay in LDS until its terms are done
+      }
     }
     if (ie) {
       // inclusion-exclusion counted the excl vertices that pass every test
@@ -383,11 +562,11 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         bool ok = y < B;
         if (ok && use_src) ok = contains(srcset, slen, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((pos >> jj) & 1u)) ok = has_nb<HUB>(g, v[jj], g.col + rs[jj], ulen[jj], y);
-        if (ok && ((pos >> J) & 1u)) ok = has_nb<HUB>(g, u, g.col + urs, urd, y);
+          if (ok && ((pos >> jj) & 1u)) ok = has_nb<BIG>(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((pos >> J) & 1u)) ok = has_nb<BIG>(g, u, g.col + urs, urd, y);
         for (int jj = 0; jj < J; ++jj)
-          if (ok && ((neg >> jj) & 1u)) ok = !has_nb<HUB>(g, v[jj], g.col + rs[jj], ulen[jj], y);
-        if (ok && ((neg >> J) & 1u)) ok = !has_nb<HUB>(g, u, g.col + urs, urd, y);
+          if (ok && ((neg >> jj) & 1u)) ok = !has_nb<BIG>(g, v[jj], g.col + rs[jj], ulen[jj], y);
+        if (ok && ((neg >> J) & 1u)) ok = !has_nb<BIG>(g, u, g.col + urs, urd, y);
         local -= ok ? 1ll : 0ll;
       }
     }
@@ -418,7 +597,7 @@ struct Split {
   int32_t r;                     // current root slot
 };
 
-template <int K, int I, bool INSTR, bool IE, bool HUB = true>
+template <int K, int I, bool INSTR, bool IE, bool BIG>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
                           uint32_t complete, int rank_prev, Acc& acc, const Split& sp,
@@ -495,10 +674,10 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
       if (ok && use_src && slot != SRC_SLOT) ok = contains(srcset, src_len, x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((pos >> j) & 1u) && slot != j) ok = has_nb<HUB>(g, v[j], g.col + rs[j], len[j], x);
+        if (ok && ((pos >> j) & 1u) && slot != j) ok = has_nb<BIG>(g, v[j], g.col + rs[j], len[j], x);
 #pragma unroll
       for (int j = 0; j < I; ++j)
-        if (ok && ((neg >> j) & 1u)) ok = !has_nb<HUB>(g, v[j], g.col + rs[j], len[j], x);
+        if (ok && ((neg >> j) & 1u)) ok = !has_nb<BIG>(g, v[j], g.col + rs[j], len[j], x);
       const unsigned long long m = __ballot(ok);
       if (ok) out[nout + mbcnt(m)] = x;
       nout += __popcll(m);
@@ -506,13 +685,13 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     if (lane == 0) M.set_len[I - 2] = nout;
     wave_sync();
     if constexpr (I == K - 2) {
-      last_level<K, INSTR, IE, HUB>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
+      last_level<K, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
     } else {
       for (int t = 0; t < nout; ++t) {
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR, IE, HUB>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
+        mat_level<K, I + 1, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
       }
     }
     cum += nout;
@@ -583,7 +762,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
       if constexpr (K == 2) {
         if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
       } else if constexpr (K == 3) {
-        last_level<K, INSTR, IE>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
+        last_level<K, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
                              end - begin, begin, acc);
       } else {
         for (int32_t i = begin; i < end; ++i) {
@@ -591,7 +770,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
           const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)r};
-          mat_level<K, 2, INSTR, IE>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
+          mat_level<K, 2, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
         }
       }
       if constexpr (PER_ROOT) {
@@ -1147,7 +1326,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const 
       rd[j] = (j < LV) ? uni(g.rowptr[v[j] + 1]) - rs[j] : 0;
     }
     const int c0 = (int)(t - piece_prefix[h]) * CH;
-    mat_level<K, LV, false, IE>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
+    mat_level<K, LV, false, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
     if constexpr (PER_ROOT) {
       unsigned long long l, hh;
       wave_sum_u128(acc.cnt, &l, &hh);
@@ -1172,8 +1351,9 @@ __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const 
 // pair through an exclusive prefix over the pairs' task counts, then a
 // first-loop task of that pair through the graph's own task prefix; the
 // task runs the same loops as k_mine and its count is added to the pair's
-// 128-bit accumulator.  The 6-7-vertex kernel probes lists by binary search
-// only: the hub bitmap test would make it spill registers.
+// 128-bit accumulator.  The census graphs are small: the loops probe lists
+// by binary search only and share the wave pair by pair (no hub bitmaps, no
+// whole-wave walks), which keeps the kernels within their registers.
 
 struct CensusPair {
   const int64_t* prefix;  // first-loop task prefix of the pair's graph (n + 1)
@@ -1214,7 +1394,7 @@ union CensusWaveMem<7> {
   WaveMem<7> m7;
 };
 
-template <int K, bool HUB>
+template <int K>
 __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
                             const CensusPair& pr, long long local, Acc& acc) {
   const int lane = lane_id();
@@ -1238,7 +1418,7 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
   if constexpr (K == 2) {
     if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
   } else if constexpr (K == 3) {
-    last_level<K, false, false, HUB>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin,
+    last_level<K, false, false, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin,
                                      begin, acc);
   } else {
     for (int32_t i = begin; i < end; ++i) {
@@ -1246,7 +1426,7 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
       rs[1] = uni(g.rowptr[v[1]]);
       rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
       const Split none{nullptr, nullptr, 0, INF, 0};
-      mat_level<K, 2, false, false, HUB>(g, plan, M, v, rs, rd, 0u, i, acc, none);
+      mat_level<K, 2, false, false, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
     }
   }
 }
@@ -1278,14 +1458,14 @@ __global__ __launch_bounds__(BLOCK) void k_census(CensusArgs A) {
       Acc acc{0ull, 0ull};
       if constexpr (KMAX == 5) {
         switch (plan.k) {
-          case 2: census_task<2, true>(g, plan, M.m2, pr, local, acc); break;
-          case 3: census_task<3, true>(g, plan, M.m3, pr, local, acc); break;
-          case 4: census_task<4, true>(g, plan, M.m4, pr, local, acc); break;
-          default: census_task<5, true>(g, plan, M.m5, pr, local, acc); break;
+          case 2: census_task<2>(g, plan, M.m2, pr, local, acc); break;
+          case 3: census_task<3>(g, plan, M.m3, pr, local, acc); break;
+          case 4: census_task<4>(g, plan, M.m4, pr, local, acc); break;
+          default: census_task<5>(g, plan, M.m5, pr, local, acc); break;
         }
       } else {
-        if (plan.k == 6) census_task<6, false>(g, plan, M.m6, pr, local, acc);
-        else census_task<7, false>(g, plan, M.m7, pr, local, acc);
+        if (plan.k == 6) census_task<6>(g, plan, M.m6, pr, local, acc);
+        else census_task<7>(g, plan, M.m7, pr, local, acc);
       }
       unsigned long long l, h;
       wave_sum_u128(acc.cnt, &l, &h);
@@ -1409,6 +1589,17 @@ gz_status launch_heavy_k(int lv, const dev::Graph& g, const Plan& plan,
 bool env_flag(const char* name) {
   const char* e = std::getenv(name);
   return e && e[0] == '1' && e[1] == '\0';
+}
+
+// A whole-number environment override within [lo, hi], else `dflt`.
+int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* e = std::getenv(name);
+  if (e && *e) {
+    char* end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (end && *end == '\0' && v >= lo && v <= hi) return (int)v;
+  }
+  return dflt;
 }
 
 // Loop bases longer than this are split (GZ_SPLIT_MIN_LEN overrides).
@@ -1874,6 +2065,9 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     float* kernel_ms, bool clique_ops) {
   Plan plan = s->plan;
   plan.ie_force = env_flag("GZ_IE_FORCE");
+  plan.long_min = env_int("GZ_LONG_MIN", 256, 1, 1 << 30);
+  plan.merge_ratio = env_int("GZ_MERGE_RATIO", 4, 0, 1 << 20);
+  plan.ie_ratio = env_int("GZ_IE_RATIO", 12, 0, 1 << 20);
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
   const int chunk = chunk_for(plan.k);
@@ -2184,11 +2378,7 @@ gz_status census_create(const gz_graph* const* graphs, int32_t n_graphs,
     c->scheds.assign(scheds, scheds + n_scheds);
   }
   std::vector<dev::Graph> gt;
-  for (int i = 0; i < n_graphs && !rc; ++i) {
-    HubMaps hm;
-    rc = graph_hubs(graphs[i], nullptr, &hm);
-    gt.push_back(device_graph(graphs[i], hm));
-  }
+  for (int i = 0; i < n_graphs && !rc; ++i) gt.push_back(device_graph(graphs[i], HubMaps{}));
   if (!rc) {
     std::vector<Plan> pt;
     for (const gz_schedule* s : c->scheds) pt.push_back(s->plan);

@@ -7,7 +7,12 @@ threshold leaves the small test graphs without hubs, so these tests force it
 low (down to every vertex being a hub), cap the bitmaps' memory so that only
 part of the leading run gets rows, switch them off, and combine them with
 the two-phase split and forced inclusion-exclusion.  Counts must stay
-bit-exact against the oracle, in total and per root."""
+bit-exact against the oracle, in total and per root.
+
+Last-loop items whose walk reaches GZ_LONG_MIN elements are counted by the
+whole wave, merging probe lists up to GZ_MERGE_RATIO times the walk's length
+through an LDS window and probing longer ones per element; both are forced
+to their extremes here (every item long; every list merged, or none)."""
 
 import os
 import sys
@@ -21,7 +26,8 @@ from paper_1911_12877_amd import gz, synth
 
 pytestmark = pytest.mark.gpu
 
-ENV = ("GZ_HUB_MIN_DEG", "GZ_HUB_MAX_KB", "GZ_SPLIT_MIN_LEN", "GZ_IE_FORCE")
+ENV = ("GZ_HUB_MIN_DEG", "GZ_HUB_MAX_KB", "GZ_SPLIT_MIN_LEN", "GZ_IE_FORCE", "GZ_LONG_MIN",
+       "GZ_MERGE_RATIO")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -145,13 +151,51 @@ def test_hubs_without_reindex():
             assert gz.count(G, gz.compile_pattern(pat, True)) == want, nm
 
 
-def test_census_with_hubs():
-    graphs = [synth.chung_lu_edges(300 + 100 * i, 2.3, 8.0, 77 + i, cap=True) for i in range(3)]
-    pats = [P.named(nm) for nm in ("c4", "diamond", "tailed_triangle", "house", "c5")]
-    Os = [oracle.from_edge_tuple(e) for e in graphs]
-    want = np.array([[oracle.count(O, p, True) for p in pats] for O in Os], dtype=np.uint64)
-    with _env(GZ_HUB_MIN_DEG=6):
-        Gs = [gz.load_edges(*e) for e in graphs]
-        c = gz.Census(Gs, [gz.compile_pattern(p, True) for p in pats])
-        got, _ = c.run()
+# (long-walk threshold, merge ratio, hub threshold): every item walked by the
+# whole wave with every list merged, with none merged (all probed, by bitmap
+# or binary search), and a middle setting; plus forced inclusion-exclusion
+LONG = [(1, 1 << 20, 1024), (1, 0, 4), (1, 0, 1024), (16, 2, 8)]
+
+
+@pytest.mark.parametrize("setting", LONG)
+def test_long_walks_match_oracle(cl_case, setting):
+    G, _, want = cl_case
+    lm, ratio, hub = setting
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        for extra in ({}, {"GZ_IE_FORCE": 1}, {"GZ_SPLIT_MIN_LEN": 0}):
+            with _env(GZ_LONG_MIN=lm, GZ_MERGE_RATIO=ratio, GZ_HUB_MIN_DEG=hub, **extra):
+                _say("long", setting, extra, nm, induced)
+                got = gz.count(G, s)
+            assert got == want[(nm, induced)], (nm, induced, setting, extra)
+
+
+def test_long_walks_every_small_pattern():
+    graphs = [synth.er_edges(14, 0.45, 81), synth.rmat_edges(6, 6, seed=82),
+              synth.chung_lu_edges(60, 2.2, 8.0, 83, cap=False)]
+    for e in graphs:
+        G = gz.load_edges(*e)
+        O = oracle.from_edge_tuple(e)
+        for k in (3, 4, 5):
+            for pat in P.connected_patterns(k):
+                for induced in (True, False):
+                    want = oracle.count(O, pat, induced)
+                    s = gz.compile_pattern(pat, induced)
+                    for ratio in (0, 1 << 20):
+                        with _env(GZ_LONG_MIN=1, GZ_MERGE_RATIO=ratio):
+                            assert gz.count(G, s) == want, (k, pat, induced, ratio)
+
+
+@pytest.mark.parametrize("nm", ["tailed_triangle", "c4", "k5e"])
+def test_long_walks_per_root(nm):
+    e = synth.rmat_edges(10, 8, seed=84)
+    G = gz.load_edges(*e)
+    O = oracle.from_edge_tuple(e)
+    pat = P.named(nm)
+    s = gz.compile_pattern(pat, True)
+    roots = np.arange(O.n, dtype=np.int32)
+    _, want = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                           roots=roots, per_root=True)
+    with _env(GZ_LONG_MIN=8, GZ_MERGE_RATIO=3, GZ_HUB_MIN_DEG=16):
+        got = gz.count_roots(G, s, roots)
     assert np.array_equal(got, want)
