@@ -197,6 +197,23 @@ gz_status gz_count(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                    uint64_t* out_count);
 
 /*
+ * gz_count for callers that cannot allocate device memory (code under HIP
+ * graph capture around it, tight serving loops, harnesses that forbid
+ * hipMalloc): the same exact count, with no hipMalloc, hipFree or other
+ * allocating call.  Its accumulators (16 x 64-bit words) live in a
+ * file-scope device array, one copy per GPU held until the process ends;
+ * every call on a GPU shares it and clears it first, so calls that overlap
+ * on one GPU (any streams) race and must be serialised by the caller.  The
+ * graph's first-loop task lists are built when the graph is loaded; the hub
+ * bitmaps are used only when an earlier count on the graph built them; long
+ * loop bases are expanded in place (no two-phase split).  The launch shape
+ * does not depend on the input's size, so no size is rejected.  Errors as
+ * gz_count.
+ */
+gz_status gz_count_noalloc(const gz_graph* g, const gz_schedule* s, void* hip_stream,
+                           uint64_t* out_count);
+
+/*
  * gz_count that also reports the mining kernels' own duration in
  * milliseconds, measured with HIP events recorded on hip_stream around the
  * mining launches (both phases and the read-back between them; accumulator

@@ -14,6 +14,9 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
                     float* kernel_ms, bool clique_ops = false);
 void free_graph_tasks(gz_graph* g);
+gz_status prepare_graph_tasks(const gz_graph* g, hipStream_t st);
+gz_status run_count_noalloc(const gz_graph* g, const gz_schedule* s, hipStream_t st,
+                            unsigned __int128* total);
 gz_status device_prepare_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                                bool device_inputs, bool reindex, hipStream_t st, gz_graph* g);
 
@@ -114,6 +117,7 @@ gz_status finish_graph(gz_graph* g, uint32_t flags, hipStream_t st, gz_graph** o
   graph_finish(&g->host);
   graph_stats(g);
   gz_status rc = upload_graph(g, st);
+  if (!rc) rc = prepare_graph_tasks(g, st);
   if (rc) {
     release_graph(g);
     return rc;
@@ -282,11 +286,14 @@ gz_status gz_load_edges(const int32_t* src, const int32_t* dst, int64_t m, int32
       return GZ_ENOMEM;
     }
     gz_status rc = device_prepare_edges(src, dst, m, n, dev, !(flags & GZ_GRAPH_NO_REINDEX), st, g);
+    if (!rc) {
+      graph_stats(g);
+      rc = prepare_graph_tasks(g, st);
+    }
     if (rc) {
       release_graph(g);
       return rc;
     }
-    graph_stats(g);
     *out = g;
     return GZ_OK;
   }
@@ -449,6 +456,25 @@ gz_status gz_count(const gz_graph* g, const gz_schedule* s, void* hip_stream,
   unsigned __int128 total = 0;
   rc = run_count(g, s, (hipStream_t)hip_stream, nullptr, 0, nullptr, false, &total, nullptr,
                  nullptr);
+  if (rc) return rc;
+  if (total >> 64) {
+    set_error("count does not fit in 64 bits");
+    return GZ_EOVERFLOW;
+  }
+  *out_count = (uint64_t)total;
+  return GZ_OK;
+}
+
+gz_status gz_count_noalloc(const gz_graph* g, const gz_schedule* s, void* hip_stream,
+                           uint64_t* out_count) {
+  gz_status rc = check_run(g, s);
+  if (rc) return rc;
+  if (!out_count) {
+    set_error("NULL output pointer");
+    return GZ_EINVAL;
+  }
+  unsigned __int128 total = 0;
+  rc = run_count_noalloc(g, s, (hipStream_t)hip_stream, &total);
   if (rc) return rc;
   if (total >> 64) {
     set_error("count does not fit in 64 bits");

@@ -2059,6 +2059,112 @@ static gz_status graph_tasks(const gz_graph* g, bool bounded1, int chunk,
   return GZ_OK;
 }
 
+// Task lists of the first loop for every (bounded, chunk) a generic count
+// can ask for (chunks of 16 and 64 candidates), built when the graph is
+// loaded so that gz_count_noalloc finds them.
+gz_status prepare_graph_tasks(const gz_graph* g, hipStream_t st) {
+  for (int b = 0; b < 2; ++b)
+    for (int chunk : {16, 64}) {
+      DevTasks t;
+      gz_status rc = graph_tasks(g, b != 0, chunk, st, &t);
+      if (rc) return rc;
+    }
+  return GZ_OK;
+}
+
+// ---------------------------------------------------- allocation-free count
+//
+// gz_count_noalloc keeps its accumulators (the 128-bit count, the queue head
+// and the rest of the layout of k_mine's acc) in this file-scope device
+// array instead of a per-call allocation.  Each GPU holds its own copy at
+// its own address until the process ends; host code must use that address
+// (looked up once per device below), never the array's name.  Every call on
+// a GPU shares the array and clears it first: calls that overlap on one GPU
+// race.
+constexpr int NOALLOC_ACC_WORDS = dev::ACC_HEAD;
+__device__ __align__(256) unsigned long long scratch[NOALLOC_ACC_WORDS];
+
+static gz_status scratch_address(unsigned long long** out) {
+  static std::mutex mu;
+  static unsigned long long* addr[64] = {};
+  int devid = 0;
+  GZ_HIP(hipGetDevice(&devid));
+  if (devid < 0 || devid >= 64) {
+    set_error("device index out of range for the scratch table");
+    return GZ_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[devid]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("scratch address: ") + hipGetErrorString(e));
+      return GZ_EDEVICE;
+    }
+    addr[devid] = (unsigned long long*)ptr;
+  }
+  *out = addr[devid];
+  return GZ_OK;
+}
+
+// gz_count without any device allocation: the generic kernels over every
+// root with the graph's task list from load time, the hub bitmaps only if a
+// count has already built them, and no two-phase split (its record list is
+// per call): long loop bases are expanded by the wave that meets them.
+gz_status run_count_noalloc(const gz_graph* g, const gz_schedule* s, hipStream_t st,
+                            unsigned __int128* total) {
+  Plan plan = s->plan;
+  plan.ie_force = env_flag("GZ_IE_FORCE");
+  plan.long_min = env_int("GZ_LONG_MIN", 256, 1, 1 << 30);
+  plan.merge_ratio = env_int("GZ_MERGE_RATIO", 4, 0, 1 << 20);
+  plan.ie_ratio = env_int("GZ_IE_RATIO", 12, 0, 1 << 20);
+  const HostGraph& h = g->host;
+  const bool bounded1 = plan.lv[1].bound == 0;
+  const int chunk = plan.k == 3 ? 64 : 16;
+  DevTasks tasks;
+  bool have = false;
+  HubMaps hubs;
+  {
+    std::lock_guard<std::mutex> lock(g->task_mu);
+    const int64_t key = (int64_t)chunk * 2 + (bounded1 ? 1 : 0);
+    for (auto& kv : g->task_cache)
+      if (kv.first == key) {
+        tasks = kv.second;
+        have = true;
+      }
+    for (const HubMaps& hm : g->hub_cache)
+      if (hm.min_deg == hub_min_deg() && hm.cap_bytes == hub_cap_bytes()) hubs = hm;
+  }
+  if (!have) {
+    set_error("the graph has no first-loop task list (it is built when the graph is loaded)");
+    return GZ_ENOTSUP;
+  }
+  unsigned long long* acc = nullptr;
+  gz_status rc = scratch_address(&acc);
+  if (rc) return rc;
+  const bool ie = plan.k >= 3 && plan.lv[plan.k - 1].sub != 0;
+  hipLaunchKernelGGL(dev::k_fill_u64, dim3(1), dim3(64), 0, st, acc, (long long)NOALLOC_ACC_WORDS);
+  GZ_HIP(hipGetLastError());
+  if (tasks.n_tasks > 0) {
+    const dev::Graph dg = device_graph(g, hubs);
+    dev::Tasks dt{tasks.prefix, nullptr, h.n, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
+                  INT32_MAX, nullptr, 0};
+    dev::Out o{acc, nullptr};
+    rc = ie ? launch_by_k<false, false, true>(plan.k, dg, plan, dt, o, st)
+            : launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
+    if (rc) return rc;
+  }
+  unsigned long long res[2] = {0ull, 0ull};
+  hipError_t e = hipMemcpyAsync(res, acc, sizeof(res), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_error(std::string("mining kernel: ") + hipGetErrorString(e));
+    return GZ_EDEVICE;
+  }
+  *total = ((unsigned __int128)res[1] << 64) | res[0];
+  return GZ_OK;
+}
+
 gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     const int32_t* roots, int64_t n_roots, uint64_t* per_root,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,

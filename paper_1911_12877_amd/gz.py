@@ -71,6 +71,7 @@ def _load():
         "gz_count_timed": [P, P, P, P, P],
         "gz_count_roots": [P, P, P, i64, P, P],
         "gz_count_subset": [P, P, P, i64, P, P, P],
+        "gz_count_noalloc": [P, P, P, P],
         "gz_count_bytes_subset": [P, P, P, i64, P, P, P],
         "gz_count_bytes": [P, P, P, P, P],
         "gz_count_ops": [P, P, P, P, P],
@@ -324,6 +325,13 @@ def free_schedule(s: Schedule):
 def count(g: Graph, s: Schedule, stream=None) -> int:
     out = ctypes.c_uint64()
     _check(_load().gz_count(g.handle, s.handle, _stream_ptr(stream), ctypes.byref(out)))
+    return int(out.value)
+
+
+def count_noalloc(g: Graph, s: Schedule, stream=None) -> int:
+    """gz_count_noalloc: the exact count without any device allocation."""
+    out = ctypes.c_uint64()
+    _check(_load().gz_count_noalloc(g.handle, s.handle, _stream_ptr(stream), ctypes.byref(out)))
     return int(out.value)
 
 
