@@ -178,20 +178,38 @@ void gz_free_schedule(gz_schedule* s);
 /*
  * Exact number of instances of the compiled pattern in the graph (each
  * instance once; |Aut(P)| times that with GZ_SCHED_NO_RESTRICT).  Runs the
- * mining kernels on hip_stream and waits for them.  Patterns of k >= 4 that
- * take the generic loops run in two phases: prefixes whose loop base is
- * longer than a threshold (2048 elements; the environment variable
- * GZ_SPLIT_MIN_LEN, a decimal integer >= 0, overrides it) are recorded by
- * the first launch and expanded in 256-element pieces by a second; the host
- * reads the record count in between.  The record list holds 2^20 prefixes
- * (GZ_SPLIT_CAP, 1..2^26, overrides it); prefixes met after it fills are
- * expanded in place.  Invalid override values are ignored.
- * The last loop of a vertex-induced pattern may count an item by
- * inclusion-exclusion over its negative lists instead of walking its
- * shortest positive list; GZ_IE_FORCE=1 makes every item with negative
- * lists take that evaluation (a test switch: the count is the same).  Errors: GZ_EINVAL (NULL handle),
- * GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified), GZ_ENOMEM,
- * GZ_EDEVICE.
+ * mining kernels on hip_stream and waits for them.  Errors: GZ_EINVAL (NULL
+ * handle), GZ_EOVERFLOW (count >= 2^64; *out_count is then unspecified),
+ * GZ_ENOMEM, GZ_EDEVICE.
+ *
+ * How the count is evaluated - never its value - can be steered by
+ * environment variables read at every call (decimal integers; invalid or
+ * out-of-range values are ignored):
+ *  - GZ_SPLIT_MIN_LEN (>= 0, default 2048) and GZ_SPLIT_CAP (1..2^26,
+ *    default 2^20): patterns of k >= 4 on the generic loops run in two
+ *    phases; prefixes whose loop base is longer than the threshold are
+ *    recorded by the first launch (up to the capacity; later ones are
+ *    expanded in place) and expanded in 256-element pieces by a second, the
+ *    host reading the record count in between.
+ *  - GZ_HUB_MIN_DEG (>= 1, default 1024) and GZ_HUB_MAX_KB (KiB, 0 turns
+ *    them off, default 8 GiB): the leading vertices of at least that degree
+ *    get a dense neighbour bitmap, built on the first count that asks for
+ *    it and kept with the graph; membership probes into their lists read
+ *    one bit.
+ *  - GZ_LONG_MIN (>= 1, default 256), GZ_MERGE_RATIO (eighths, default 4)
+ *    and GZ_IE_RATIO (eighths, default 12): last-loop items whose walk
+ *    reaches GZ_LONG_MIN elements are counted by a whole wave, merging
+ *    probe lists at most GZ_MERGE_RATIO/8 times the walk's length; an item
+ *    of a vertex-induced pattern counts by inclusion-exclusion over its
+ *    negative lists when that costs less than GZ_IE_RATIO/8 of walking its
+ *    shortest positive list.  GZ_IE_FORCE=1 makes every item with negative
+ *    lists take inclusion-exclusion.
+ *  - GZ_CLIQUE_MAX_LO (0..1024, default 1024): clique schedules run on
+ *    per-root bit rows (see gz_count_ops) for roots with at most this many
+ *    first-loop candidates; roots with more take the generic loops.
+ *  - GZ_ACC_SEED (test only): the count's 128-bit accumulator (and every
+ *    per-root slot of gz_count_roots) starts at this value instead of 0, so
+ *    the result is shifted by it; tests drive the overflow checks with it.
  */
 gz_status gz_count(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                    uint64_t* out_count);
@@ -278,7 +296,8 @@ gz_status gz_count_bytes_subset(const gz_graph* g, const gz_schedule* s,
  * gz_count_ops runs that path instrumented and returns the number of 32-bit
  * lane operations of those row intersections (each 64-bit row word ANDed
  * costs 2, each 64-bit popcount 2) together with the count.  GZ_ENOTSUP for
- * schedules that do not take the clique path.
+ * schedules that do not take the clique path, or when some root has more
+ * first-loop candidates than the bit rows hold.
  */
 gz_status gz_count_ops(const gz_graph* g, const gz_schedule* s, void* hip_stream,
                        uint64_t* out_ops, uint64_t* out_count);

@@ -126,8 +126,9 @@ struct DevTasks {
 };
 
 // Root lists of the clique path: light roots (3 <= lo <= 64) for the wave
-// kernel, heavy roots (lo > 64) for the workgroup kernel, the latter in order
-// of decreasing lo so that the largest start first.  Device arrays.
+// kernel, heavy roots (64 < lo <= max_lo) for the workgroup kernel, the
+// latter in order of decreasing lo so that the largest start first, and the
+// roots above max_lo for the generic kernels.  Device arrays.
 struct CliqueLists {
   int32_t* light_v = nullptr;
   int32_t* light_r = nullptr;
@@ -142,6 +143,14 @@ struct CliqueLists {
   int32_t n_buckets = 0;
   int32_t bucket_w[4] = {0, 0, 0, 0};
   int64_t bucket_begin[5] = {0, 0, 0, 0, 0};
+  // roots with more candidates than the bit rows hold (max_lo) take the
+  // generic loops: vertices, output slots and their first-loop task prefix
+  int32_t max_lo = 0;
+  int32_t* over_v = nullptr;
+  int32_t* over_r = nullptr;
+  int64_t* over_prefix = nullptr;
+  int64_t n_over = 0;
+  int64_t over_tasks = 0;
 };
 
 // Dense neighbour bitmaps of the leading vertices 0..n_hub-1, which after

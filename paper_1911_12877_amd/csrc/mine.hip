@@ -64,6 +64,7 @@ struct HeavyItem;
 struct Tasks {
   const int64_t* __restrict__ prefix;  // n_roots + 1
   const int32_t* __restrict__ roots;   // nullptr: root r is vertex r
+  const int32_t* __restrict__ slots;   // per-root output slot of root r (nullptr: r)
   int64_t n_roots;
   int64_t n_tasks;
   int32_t chunk;
@@ -72,12 +73,14 @@ struct Tasks {
   int32_t heavy_min;                   // split loop bases longer than this
   HeavyItem* heavy;                    // second-phase list (nullptr: no split)
   long long heavy_cap;
+  int32_t queue;                       // acc index of the queue head
 };
 
 // acc[0..1]: 128-bit count; acc[2..3]: 128-bit bytes (or operations);
-// acc[4]: queue head; acc[5]: per-root overflow flag; acc[6]: split record
-// count; acc[8..11]: queue heads of the clique workgroup launches; per-root
-// counts start at acc[ACC_HEAD]
+// acc[4]: queue head (k_mine, k_clique_wave); acc[5]: per-root overflow
+// flag; acc[6]: split record count; acc[7]: queue head of the generic launch
+// over a clique count's roots beyond the bit rows; acc[8..11]: queue heads of
+// the clique workgroup launches; per-root counts start at acc[ACC_HEAD]
 constexpr int ACC_BLOCK_QUEUES = 8;
 constexpr int ACC_HEAD = 16;
 struct Out {
@@ -738,7 +741,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
 
   for (;;) {
     long long t0 = 0;
-    if (lane == 0) t0 = (long long)atomicAdd(o.acc + 4, (unsigned long long)T.batch);
+    if (lane == 0) t0 = (long long)atomicAdd(o.acc + T.queue, (unsigned long long)T.batch);
     t0 = __shfl(t0, 0, WAVE);
     if (t0 >= T.n_tasks) break;
     const long long t1 = min(t0 + (long long)T.batch, T.n_tasks);
@@ -750,6 +753,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
         if (T.prefix[mid] <= t) lo = mid + 1; else hi = mid;
       }
       const long long r = lo - 1;
+      const long long slot = T.slots ? T.slots[r] : r;
       const int32_t v0 = uni(T.roots ? T.roots[r] : (int32_t)r);
       const int32_t rs0 = uni(g.rowptr[v0]);
       const int32_t rd0 = uni(g.rowptr[v0 + 1]) - rs0;
@@ -769,7 +773,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
           v[1] = uni(g.col[rs0 + i]);
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
-          const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)r};
+          const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)slot};
           mat_level<K, 2, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
         }
       }
@@ -777,7 +781,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
         unsigned long long l, h;
         wave_sum_u128(acc.cnt, &l, &h);
         if (lane == 0) {
-          unsigned long long old = atomicAdd(o.per_root + r, l);
+          unsigned long long old = atomicAdd(o.per_root + slot, l);
           if (h || old + l < old) atomicOr(o.acc + 5, 1ull);
         }
         acc.cnt = 0;
@@ -1479,6 +1483,16 @@ __global__ void k_fill_u64(unsigned long long* p, long long n) {
   for (; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0ull;
 }
 
+// Test-only preset of the accumulators (GZ_ACC_SEED): the count's low word
+// and every per-root slot start at `seed`, so that a small count carries
+// into the high word or out of a per-root slot.
+__global__ void k_seed_acc(unsigned long long* acc, unsigned long long* per_root, long long n_roots,
+                           unsigned long long seed) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) acc[0] = seed;
+  for (; i < n_roots; i += (long long)gridDim.x * blockDim.x) per_root[i] = seed;
+}
+
 // Neighbour bitmaps of vertices 0..n_hub-1 (rows cleared beforehand): one
 // workgroup per hub row at a time, each thread setting the bits of a strided
 // share of the hub's neighbours.
@@ -1497,6 +1511,8 @@ __global__ void k_hub_bits(const int32_t* __restrict__ rowptr, const int32_t* __
 }  // namespace dev
 
 // ------------------------------------------------------------ host side
+
+static gz_status upload_prefix(const std::vector<int64_t>& pre, int64_t** out, hipStream_t st);
 
 namespace {
 
@@ -1589,6 +1605,17 @@ gz_status launch_heavy_k(int lv, const dev::Graph& g, const Plan& plan,
 bool env_flag(const char* name) {
   const char* e = std::getenv(name);
   return e && e[0] == '1' && e[1] == '\0';
+}
+
+// GZ_ACC_SEED: a test-only preset of the count accumulators (decimal
+// 64-bit value), 0 when unset or malformed.  It shifts every count by the
+// seed; tests use it to drive the 128-bit carry and the overflow checks.
+unsigned long long acc_seed() {
+  const char* e = std::getenv("GZ_ACC_SEED");
+  if (!e || !*e || *e == '-') return 0ull;
+  char* end = nullptr;
+  const unsigned long long v = std::strtoull(e, &end, 10);
+  return (end && *end == '\0') ? v : 0ull;
 }
 
 // A whole-number environment override within [lo, hi], else `dflt`.
@@ -1819,15 +1846,21 @@ gz_status upload_i32(const std::vector<int32_t>& v, int32_t** out, hipStream_t s
 }
 
 gz_status build_clique_lists(const HostGraph& h, const int32_t* roots, int64_t n_roots,
-                             hipStream_t st, CliqueLists* out) {
-  std::vector<int32_t> lv, lr;
+                             int32_t max_lo, int32_t chunk, hipStream_t st, CliqueLists* out) {
+  std::vector<int32_t> lv, lr, ov, orr;
+  std::vector<int64_t> opre(1, 0);
   std::vector<std::pair<int32_t, int32_t>> hv;  // (lo, index)
   const int64_t nr = roots ? n_roots : h.n;
+  out->max_lo = max_lo;
   for (int64_t i = 0; i < nr; ++i) {
     const int32_t v = roots ? roots[i] : (int32_t)i;
     const int32_t d = h.lo[v];
     if (d < 3) continue;
-    if (d <= dev::CW) {
+    if (d > max_lo) {
+      ov.push_back(v);
+      orr.push_back((int32_t)i);
+      opre.push_back(opre.back() + (d + chunk - 1) / chunk);
+    } else if (d <= dev::CW) {
       lv.push_back(v);
       lr.push_back((int32_t)i);
     } else {
@@ -1887,18 +1920,26 @@ gz_status build_clique_lists(const HostGraph& h, const int32_t* roots, int64_t n
   if (!rc) rc = upload_i32(lr, &out->light_r, st);
   if (!rc) rc = upload_i32(hvv, &out->heavy_v, st);
   if (!rc) rc = upload_i32(hvr, &out->heavy_r, st);
+  if (!rc && !ov.empty()) {
+    rc = upload_i32(ov, &out->over_v, st);
+    if (!rc) rc = upload_i32(orr, &out->over_r, st);
+    if (!rc) rc = upload_prefix(opre, &out->over_prefix, st);
+  }
   if (!rc && hipStreamSynchronize(st) != hipSuccess) {
     set_error("clique root list upload failed");
     rc = GZ_EDEVICE;
   }
   out->n_light = (int64_t)lv.size();
   out->n_heavy = (int64_t)hvv.size();
+  out->n_over = (int64_t)ov.size();
+  out->over_tasks = opre.back();
   return rc;
 }
 
 void free_clique_lists(CliqueLists* c) {
-  for (int32_t* p : {c->light_v, c->light_r, c->heavy_v, c->heavy_r})
+  for (int32_t* p : {c->light_v, c->light_r, c->heavy_v, c->heavy_r, c->over_v, c->over_r})
     if (p) (void)hipFree(p);
+  if (c->over_prefix) (void)hipFree(c->over_prefix);
   *c = CliqueLists();
 }
 
@@ -2147,8 +2188,8 @@ gz_status run_count_noalloc(const gz_graph* g, const gz_schedule* s, hipStream_t
   GZ_HIP(hipGetLastError());
   if (tasks.n_tasks > 0) {
     const dev::Graph dg = device_graph(g, hubs);
-    dev::Tasks dt{tasks.prefix, nullptr, h.n, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
-                  INT32_MAX, nullptr, 0};
+    dev::Tasks dt{tasks.prefix, nullptr, nullptr, h.n, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
+                  INT32_MAX, nullptr, 0, 4};
     dev::Out o{acc, nullptr};
     rc = ie ? launch_by_k<false, false, true>(plan.k, dg, plan, dt, o, st)
             : launch_by_k<false, false>(plan.k, dg, plan, dt, o, st);
@@ -2213,16 +2254,36 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
     set_error("device allocation of the accumulators failed");
     rc = GZ_ENOMEM;
   }
-  // clique fast path: K_k (k >= 4) with chain bounds, rows of at most 16 words
-  const bool use_clique = !instr && plan.k >= 4 && is_clique_chain(plan) && g->max_lo <= 1024;
-  if (!rc && clique_ops && (!use_clique || pr)) {
+  // clique fast path: K_k (k >= 4) with chain bounds; roots with more
+  // candidates than the bit rows hold (GZ_CLIQUE_MAX_LO, at most 1024)
+  // take the generic loops through a root list
+  const bool use_clique = !instr && plan.k >= 4 && is_clique_chain(plan);
+  const int32_t clique_max_lo = env_int("GZ_CLIQUE_MAX_LO", 1024, 0, 1024);
+  CliqueLists own_lists;
+  const CliqueLists* lists = nullptr;
+  if (!rc && use_clique) {
+    if (!pr && clique_max_lo == 1024) {
+      std::lock_guard<std::mutex> lock(g->task_mu);
+      if (!g->clique_ready) {
+        rc = build_clique_lists(h, nullptr, 0, 1024, 1, st, &g->clique_all);
+        if (rc) free_clique_lists(&g->clique_all);
+        else g->clique_ready = true;
+      }
+      lists = &g->clique_all;
+    } else {
+      rc = build_clique_lists(h, roots, nr, clique_max_lo, 1, st, &own_lists);
+      lists = &own_lists;
+    }
+  }
+  const bool over = use_clique && lists && lists->n_over > 0;
+  if (!rc && clique_ops && (!use_clique || pr || over)) {
     set_error("operation counts exist only for the clique path over all roots");
     rc = GZ_ENOTSUP;
   }
   // inclusion-exclusion in the last loop: wherever it has negative lists
   const bool ie = !instr && plan.k >= 3 && plan.lv[plan.k - 1].sub != 0;
   // second phase of the generic path: long loop bases split into pieces
-  const bool split = !rc && !use_clique && !instr && plan.k >= 4;
+  const bool split = !rc && (!use_clique || over) && !instr && plan.k >= 4;
   const long long heavy_cap = split ? split_cap() : 0;
   dev::HeavyItem* d_heavy = nullptr;
   if (split && hipMalloc(&d_heavy, sizeof(dev::HeavyItem) * heavy_cap) != hipSuccess) {
@@ -2231,30 +2292,17 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
   }
   // neighbour bitmaps of the hubs for the generic path's probes
   HubMaps hubs;
-  if (!rc && !use_clique) rc = graph_hubs(g, st, &hubs);
+  if (!rc && (!use_clique || over)) rc = graph_hubs(g, st, &hubs);
   void* heavy_scratch = nullptr;
-  CliqueLists own_lists;
-  const CliqueLists* lists = nullptr;
-  if (!rc && use_clique) {
-    if (!pr) {
-      std::lock_guard<std::mutex> lock(g->task_mu);
-      if (!g->clique_ready) {
-        rc = build_clique_lists(h, nullptr, 0, st, &g->clique_all);
-        if (rc) free_clique_lists(&g->clique_all);
-        else g->clique_ready = true;
-      }
-      lists = &g->clique_all;
-    } else {
-      rc = build_clique_lists(h, roots, nr, st, &own_lists);
-      lists = &own_lists;
-    }
-  }
   if (!rc) {
     hipLaunchKernelGGL(dev::k_fill_u64, dim3((unsigned)std::min<long long>((n_acc + 255) / 256, 4096)),
                        dim3(256), 0, st, d_acc, n_acc);
+    if (const unsigned long long seed = acc_seed())
+      hipLaunchKernelGGL(dev::k_seed_acc, dim3((unsigned)std::min<long long>((nr + 255) / 256 + 1, 4096)),
+                         dim3(256), 0, st, d_acc, d_acc + dev::ACC_HEAD, out_pr ? nr : 0ll, seed);
     const dev::Graph dg = device_graph(g, hubs);
-    dev::Tasks dt{tasks.prefix, d_roots, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
-                  split_min_len(), d_heavy, split ? heavy_cap : 0};
+    dev::Tasks dt{tasks.prefix, d_roots, nullptr, nr, tasks.n_tasks, chunk, bounded1 ? 1 : 0, 1,
+                  split_min_len(), d_heavy, split ? heavy_cap : 0, 4};
     dev::Out o{d_acc, d_acc + dev::ACC_HEAD};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (kernel_ms) {
@@ -2270,6 +2318,15 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
         rc = out_pr ? launch_clique<true, false>(plan.k, dg, *lists, o, st)
                 : (clique_ops ? launch_clique<false, true>(plan.k, dg, *lists, o, st)
                               : launch_clique<false, false>(plan.k, dg, *lists, o, st));
+        if (!rc && over) {
+          // few roots with dense candidate sets: one first-loop candidate
+          // per task and every base longer than a piece split
+          const dev::Tasks ot{lists->over_prefix, lists->over_v, lists->over_r, lists->n_over,
+                              lists->over_tasks, 1, 1, 1, std::min(split_min_len(), dev::CH),
+                              d_heavy, heavy_cap, 7};
+          rc = out_pr ? launch_by_k<true, false>(plan.k, dg, plan, ot, o, st)
+                      : launch_by_k<false, false>(plan.k, dg, plan, ot, o, st);
+        }
       } else if (out_pr && instr) rc = launch_by_k<true, true>(plan.k, dg, plan, dt, o, st);
       else if (out_pr) rc = ie ? launch_by_k<true, false, true>(plan.k, dg, plan, dt, o, st)
                            : launch_by_k<true, false>(plan.k, dg, plan, dt, o, st);

@@ -251,6 +251,63 @@ def test_clique_paths_closed_forms():
             assert gz.count(G, gz.compile_pattern(P.named(f"k{k}"), True)) == math.comb(n, k)
 
 
+def test_clique_widest_rows_closed_forms():
+    """K_700: after reindexing root v has the v candidates 0..v-1, so roots
+    above 512 build rows of 9 to 11 words, the widest size class.  Totals
+    are C(700, k) and the count of root v is C(v, k - 1): the k-cliques whose
+    largest id is v."""
+    n = 700
+    G = gz.load_edges(*synth.complete_edges(n))
+    roots = np.arange(n, dtype=np.int32)
+    for k in (4, 5):
+        s = gz.compile_pattern(P.named(f"k{k}"), True)
+        _say("K_700 clique closed form", k)
+        assert gz.count(G, s) == math.comb(n, k)
+        per = gz.count_roots(G, s, roots)
+        want = np.array([math.comb(v, k - 1) for v in range(n)], dtype=np.uint64)
+        assert np.array_equal(per, want), k
+    assert math.comb(n, 4) == 9_918_641_075 and math.comb(n, 5) == 1_380_674_837_640
+
+
+def test_clique_roots_over_capacity_take_generic_loops():
+    """Bit rows hold at most 1024 candidates: on K_1040 the roots 1025..1039
+    take the generic loops through a root list while the others stay on the
+    clique kernels, and per-root counts land in their own slots.  The gate
+    is also forced low (GZ_CLIQUE_MAX_LO) so that most roots of K_300 and of
+    an R-MAT graph cross it."""
+    import os
+    n = 1040
+    G = gz.load_edges(*synth.complete_edges(n))
+    s = gz.compile_pattern(P.named("k4"), True)
+    assert gz.count(G, s) == math.comb(n, 4)
+    roots = np.array([3, 1039, 500, 1030, 1024, 1025, 7], np.int32)
+    want = np.array([math.comb(int(v), 3) for v in roots], dtype=np.uint64)
+    assert np.array_equal(gz.count_roots(G, s, roots), want)
+    try:
+        os.environ["GZ_CLIQUE_MAX_LO"] = "100"
+        G = gz.load_edges(*synth.complete_edges(300))
+        for k in (4, 5):
+            s = gz.compile_pattern(P.named(f"k{k}"), True)
+            assert gz.count(G, s) == math.comb(300, k), k
+            per = gz.count_roots(G, s, np.arange(300, dtype=np.int32))
+            assert np.array_equal(per, np.array([math.comb(v, k - 1) for v in range(300)],
+                                                dtype=np.uint64)), k
+        e = synth.rmat_edges(10, 16, seed=114)
+        G, O = _pair(e)
+        roots = np.arange(O.n, dtype=np.int32)
+        for gate in ("0", "8", "40"):
+            os.environ["GZ_CLIQUE_MAX_LO"] = gate
+            for k in (4, 5):
+                pat = P.named(f"k{k}")
+                s = gz.compile_pattern(pat, True)
+                total, per = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                                          roots=roots, per_root=True)
+                assert gz.count(G, s) == total, (gate, k)
+                assert np.array_equal(gz.count_roots(G, s, roots), per), (gate, k)
+    finally:
+        os.environ.pop("GZ_CLIQUE_MAX_LO", None)
+
+
 @pytest.mark.parametrize("which", ["er_dense", "rmat10", "cl_core"])
 def test_clique_paths_vs_oracle(which):
     if which == "er_dense":
