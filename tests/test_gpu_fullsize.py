@@ -93,6 +93,30 @@ def test_rmat20_cliques(rmat20, k):
     per = gz.count_roots(G, s, allr)
     assert int(per.astype(object).sum()) == total
     _say(f"rmat20 k{k} total {total}")
+    # the full count against the oracle's, stored by an oracle-only script
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "rmat20_clique_totals.json")) as f:
+        assert total == int(json.load(f)["counts"][f"k{k}"])
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_rmat20_cliques_stored_roots(rmat20, k):
+    """K4/K5 per-root counts against the oracle's stored values at roots
+    chosen by candidate count: the 16 widest (rows of 9-11 words), seeded
+    roots of every size class, and the top-degree roots."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "rmat20_clique_roots.json")
+    if not os.path.exists(path):
+        pytest.skip("rmat20_clique_roots.json not generated")
+    with open(path) as f:
+        entry = json.load(f)[f"k{k}"]
+    G, _ = rmat20
+    s = gz.compile_pattern(P.named(f"k{k}"), True)
+    roots = np.array(entry["roots"], np.int32)
+    want = np.array([int(c) for c in entry["counts"]], np.uint64)
+    assert max(entry["lo"]) > 640
+    _say(f"rmat20 k{k}: gpu on {roots.size} stored roots")
+    assert np.array_equal(gz.count_roots(G, s, roots), want)
 
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
