@@ -371,8 +371,13 @@ gz_status gz_schedule_features(const gz_graph* g, const uint8_t* adj, int32_t k,
                                float* out);
 
 /* Install (copy) a model for GZ_SCHED_LEARNED, process-wide; params NULL
- * removes it.  D must be GZ_FEATURES, 1 <= H <= 1024. */
-gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H);
+ * removes it.  D must be GZ_FEATURES, 1 <= H <= 1024.  margin (log10 of
+ * time, >= 0): a learned choice replaces the analytic model's pick only
+ * when the network predicts it faster by more than margin.  k_max (2..8):
+ * the largest pattern in the model's training corpus; larger patterns keep
+ * the analytic pick. */
+gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H, float margin,
+                            int32_t k_max);
 
 /* gz_compile_pattern with the graph the schedule will run on.  With
  * GZ_SCHED_LEARNED and an installed model the distinct schedule of lowest

@@ -28,6 +28,8 @@ namespace {
 std::mutex g_model_mu;
 std::vector<float> g_model;
 int g_model_h = 0;
+float g_model_margin = 0.0f;
+int32_t g_model_kmax = 0;
 
 double lg(double x) { return std::log10(std::max(x, 1e-30)); }
 float clampf(double x, double lo, double hi) { return (float)std::min(hi, std::max(lo, x)); }
@@ -151,19 +153,26 @@ gz_status gz_schedule_features(const gz_graph* g, const uint8_t* adj, int32_t k,
   return GZ_OK;
 }
 
-gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H) {
+gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H, float margin,
+                            int32_t k_max) {
   std::lock_guard<std::mutex> lock(g_model_mu);
   if (!params) {
     g_model.clear();
     g_model_h = 0;
+    g_model_margin = 0.0f;
+    g_model_kmax = 0;
     return GZ_OK;
   }
-  if (D != GZ_FEATURES || H < 1 || H > 1024) {
-    set_error("cost model must have D == GZ_FEATURES and 1 <= H <= 1024");
+  if (D != GZ_FEATURES || H < 1 || H > 1024 || !(margin >= 0.0f && margin < 100.0f) ||
+      k_max < 2 || k_max > kMaxK) {
+    set_error("cost model must have D == GZ_FEATURES, 1 <= H <= 1024, 0 <= margin < 100 "
+              "and 2 <= k_max <= 8");
     return GZ_EINVAL;
   }
   g_model.assign(params, params + mlp_param_count(D, H));
   g_model_h = H;
+  g_model_margin = margin;
+  g_model_kmax = k_max;
   return GZ_OK;
 }
 
@@ -177,13 +186,20 @@ gz_status gz_compile_pattern_graph(const gz_graph* g, const uint8_t* adj, int32_
   if (!read_pattern_checked(adj, k, &p)) return GZ_EINVAL;
   std::vector<float> model;
   int H = 0;
+  float margin = 0.0f;
+  int32_t kmax = 0;
   {
     std::lock_guard<std::mutex> lock(g_model_mu);
     model = g_model;
     H = g_model_h;
+    margin = g_model_margin;
+    kmax = g_model_kmax;
   }
   const uint32_t rest = flags & ~(uint32_t)GZ_SCHED_LEARNED;
-  if (!(flags & GZ_SCHED_LEARNED) || model.empty()) return build_schedule_for(p, induced, rest, nullptr, out);
+  // no model, or a pattern larger than any in its corpus (features of loops
+  // the network never saw): the analytic model's pick
+  if (!(flags & GZ_SCHED_LEARNED) || model.empty() || p.k > kmax)
+    return build_schedule_for(p, induced, rest, nullptr, out);
   std::vector<Perm> aut = automorphisms(p);
   std::vector<Perm> ds = explore_schedules(p, aut);
   const int n = (int)ds.size();
@@ -196,6 +212,19 @@ gz_status gz_compile_pattern_graph(const gz_graph* g, const uint8_t* adj, int32_
   int best = 0;
   for (int i = 1; i < n; ++i)
     if (y[i] < y[best] - 1e-6f * std::max(1.0f, std::fabs(y[best]))) best = i;
+  // the analytic model's pick stays unless the network predicts the best
+  // schedule faster by more than its validation error (log10 time)
+  gz_schedule* analytic = nullptr;
+  rc = build_schedule_for(p, induced, rest, nullptr, &analytic);
+  if (rc) return rc;
+  int an = -1;
+  for (int i = 0; i < n && an < 0; ++i)
+    if (std::equal(ds[i].begin(), ds[i].end(), analytic->order)) an = i;
+  if (an >= 0 && y[an] - y[best] <= margin) {
+    *out = analytic;
+    return GZ_OK;
+  }
+  gz_free_schedule(analytic);
   return build_schedule_for(p, induced, rest, ds[best].data(), out);
 }
 

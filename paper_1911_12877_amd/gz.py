@@ -80,7 +80,7 @@ def _load():
         "gz_census_tune": [P, P, P],
         "gz_prepare_edges": [P, P, i64, i32, u32, P, P, P, P, P],
         "gz_schedule_features": [P, P, i32, i32, P, P],
-        "gz_set_cost_model": [P, i32, i32],
+        "gz_set_cost_model": [P, i32, i32, ctypes.c_float, i32],
         "gz_compile_pattern_graph": [P, P, i32, i32, u32, P],
         "gz_mlp_forward": [P, P, i32, i32, i32, i32, P, P],
         "gz_mlp_loss_grad": [P, P, P, i32, i32, i32, P, P, P],
@@ -406,13 +406,16 @@ def schedule_features(g: Graph, adj, order, induced=True):
     return out
 
 
-def set_cost_model(params, H=None):
-    """gz_set_cost_model: install FP32 parameters (None removes the model)."""
+def set_cost_model(params, H=None, margin=0.0, k_max=8):
+    """gz_set_cost_model: install FP32 parameters (None removes the model);
+    margin: the predicted gain (log10 time) a learned choice must exceed;
+    k_max: the largest pattern size the model was trained on."""
     if params is None:
-        _check(_load().gz_set_cost_model(None, FEATURES, 1))
+        _check(_load().gz_set_cost_model(None, FEATURES, 1, ctypes.c_float(0.0), 8))
         return
     p = _np(params, np.float32)
-    _check(_load().gz_set_cost_model(p.ctypes.data, FEATURES, H))
+    _check(_load().gz_set_cost_model(p.ctypes.data, FEATURES, H, ctypes.c_float(margin),
+                                     int(k_max)))
 
 
 def compile_pattern_graph(g: Graph, adj, induced=True, flags=SCHED_LEARNED) -> Schedule:

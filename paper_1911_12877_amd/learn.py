@@ -11,8 +11,15 @@ backward and Adam); ranking at compile time uses BF16 inference.  The
 patterns whose schedules the model is evaluated on (the 6-cycle with one
 chord, K6 minus an edge, K7 minus an edge) are never in the corpus.
 
+A learned choice replaces the analytic model's pick only when the network
+predicts it faster by more than twice its validation error (group-wise
+cross-validation over the corpus, stored with the weights as `margin`), and
+only for patterns no larger than the corpus's (`k_max`): the features of
+further loops were never seen in training.
+
 Command line (GPU):  python -m paper_1911_12877_amd.learn collect OUT.npz
                      python -m paper_1911_12877_amd.learn train IN.npz [MODEL.npz]
+                     python -m paper_1911_12877_amd.learn margin IN.npz [MODEL.npz]
 """
 
 from __future__ import annotations
@@ -231,21 +238,63 @@ def train(X, yc, H=H_DEFAULT, steps=3000, lr=3e-3, seed=0, log=None):
     return P.cpu().numpy(), losses
 
 
-def save(params, H, path=MODEL_PATH):
+def cv_margin(X, y, grp, folds=5, seed=0, log=None, **kw):
+    """The model's validation error in log10 time: groups (one pattern on one
+    graph) are dealt to `folds` folds; a network trained on the other folds
+    predicts each held-out group, and the root mean square of its centred
+    prediction error over all held-out schedules is returned."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    groups = np.unique(grp)
+    fold_of = dict(zip(groups, rng.permutation(len(groups)) % folds))
+    fold = np.array([fold_of[g] for g in grp])
+    yc = centred(y, grp)
+    err = np.zeros(len(y))
+    for f in range(folds):
+        tr, te = fold != f, fold == f
+        P, _ = train(X[tr], centred(y[tr], grp[tr]), **kw)
+        pred = gz.mlp_forward(torch.from_numpy(P).cuda(),
+                              torch.from_numpy(np.ascontiguousarray(X[te], np.float32)).cuda(),
+                              kw.get("H", H_DEFAULT), bf16=True).cpu().numpy().astype(np.float64)
+        for g in np.unique(grp[te]):
+            m = grp[te] == g
+            err[np.nonzero(te)[0][m]] = (pred[m] - pred[m].mean()) - yc[te][m]
+        if log:
+            log(f"fold {f}: held-out rms {np.sqrt(np.mean(err[te] ** 2)):.4f}", flush=True)
+    return float(np.sqrt(np.mean(err ** 2)))
+
+
+def corpus_k_max(X):
+    """Largest pattern size among corpus rows: 1 + the loops present (the
+    first of each loop's 14 features is its presence flag)."""
+    present = np.asarray(X)[:, [14 * i for i in range(7)]] > 0.5
+    return int(1 + present.sum(axis=1).max())
+
+
+# a learned choice must beat the analytic pick's predicted time by this many
+# validation errors (two: about 95% confidence for a normal error)
+MARGIN_SIGMAS = 2.0
+
+
+def save(params, H, path=MODEL_PATH, margin=0.0, k_max=8):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.savez(path, params=np.asarray(params, dtype=np.float32), H=np.int32(H),
-             D=np.int32(gz.FEATURES))
+             D=np.int32(gz.FEATURES), margin=np.float32(margin), k_max=np.int32(k_max))
 
 
 def load(path=MODEL_PATH):
+    """(params, H, validation error, k_max); 0 and 8 for a file written
+    without them."""
     z = np.load(path)
-    return z["params"].astype(np.float32), int(z["H"])
+    margin = float(z["margin"]) if "margin" in z.files else 0.0
+    k_max = int(z["k_max"]) if "k_max" in z.files else 8
+    return z["params"].astype(np.float32), int(z["H"]), margin, k_max
 
 
 def install(path=MODEL_PATH):
     """Install the bundled (or given) model for GZ_SCHED_LEARNED."""
-    params, H = load(path)
-    gz.set_cost_model(params, H)
+    params, H, err, k_max = load(path)
+    gz.set_cost_model(params, H, MARGIN_SIGMAS * err, k_max)
     return params, H
 
 
@@ -256,9 +305,20 @@ def main(argv):
         z = np.load(argv[1])
         X, y, grp = z["X"], z["y"], z["group"]
         P, losses = train(X, centred(y, grp), log=print)
+        margin = cv_margin(X, y, grp, log=print)
         out = argv[2] if len(argv) > 2 else MODEL_PATH
-        save(P, H_DEFAULT, out)
-        print(f"saved {out}; final loss {losses[-1]:.4f}")
+        save(P, H_DEFAULT, out, margin, corpus_k_max(X))
+        print(f"saved {out}; final loss {losses[-1]:.4f}, validation error {margin:.4f}")
+    elif len(argv) >= 2 and argv[0] == "margin":
+        # the validation error of a saved model's training recipe, stored
+        # beside its unchanged weights
+        z = np.load(argv[1])
+        X, y, grp = z["X"], z["y"], z["group"]
+        out = argv[2] if len(argv) > 2 else MODEL_PATH
+        params, H, _, _ = load(out)
+        margin = cv_margin(X, y, grp, log=print)
+        save(params, H, out, margin, corpus_k_max(X))
+        print(f"saved {out}; validation error {margin:.4f}, k_max {corpus_k_max(X)}")
     else:
         print(__doc__)
         return 2
