@@ -55,65 +55,78 @@ bool schedule_valid(const Pattern& p, const int8_t* order) {
   return true;
 }
 
-// Algorithm 3.  Candidates of the next step are visited in ascending label
-// order; the automorphisms that fix the scheduled prefix split them into
-// orbits and only the first member of each orbit is expanded.  The candidate
-// set of the child is (valid_next U N(v)) without the scheduled vertices.
-static void explore_rec(const Pattern& p, Perm& sched, uint32_t in_sched,
-                        const std::vector<Perm>& group, uint32_t valid_next,
-                        std::vector<Perm>* out) {
-  if ((int)sched.size() == p.k) {
-    out->push_back(sched);
+// Orbits of a permutation group on a set of labels: orbit_of[v] is the
+// smallest label of v's orbit (for v in `set`; the set must be closed under
+// the group).
+static void orbit_minima(const std::vector<Perm>& group, uint32_t set, int k, int8_t* orbit_of) {
+  for (int v = 0; v < k; ++v) orbit_of[v] = (int8_t)v;
+  for (int v = 0; v < k; ++v) {
+    if (!(set >> v & 1)) continue;
+    for (const Perm& g : group) orbit_of[v] = std::min<int8_t>(orbit_of[v], g[v]);
+  }
+}
+
+// The pointwise stabiliser of v within a group.
+static std::vector<Perm> fixing(const std::vector<Perm>& group, int v) {
+  std::vector<Perm> out;
+  for (const Perm& g : group)
+    if (g[v] == v) out.push_back(g);
+  return out;
+}
+
+// Distinct schedules (Algorithm 3).  Two prefixes that an automorphism maps
+// onto each other have the same completions up to that automorphism, so of
+// the vertices that may come next (all of them first, afterwards the
+// unscheduled neighbours of the prefix) only one per orbit of the group
+// fixing the prefix pointwise is tried: the orbit's smallest label, in
+// ascending order.  `group` fixes the prefix; `frontier` holds the
+// unscheduled neighbours of the prefix.
+static void distinct_orders(const Pattern& p, Perm& prefix, uint32_t placed,
+                            const std::vector<Perm>& group, uint32_t frontier,
+                            std::vector<Perm>* out) {
+  if ((int)prefix.size() == p.k) {
+    out->push_back(prefix);
     return;
   }
-  uint32_t iterate = sched.empty() ? (1u << p.k) - 1 : valid_next;
-  uint32_t processed = 0;
+  const uint32_t next = prefix.empty() ? (1u << p.k) - 1 : frontier;
+  int8_t orbit_of[kMaxK];
+  orbit_minima(group, next, p.k, orbit_of);
   for (int v = 0; v < p.k; ++v) {
-    if (!(iterate >> v & 1) || (processed >> v & 1)) continue;
-    std::vector<Perm> stab;
-    for (const Perm& x : group) {
-      if (x[v] == v)
-        stab.push_back(x);
-      else
-        processed |= 1u << x[v];
-    }
-    sched.push_back((int8_t)v);
-    uint32_t now = in_sched | (1u << v);
-    explore_rec(p, sched, now, stab, (valid_next | nbr_mask(p, v)) & ~now, out);
-    sched.pop_back();
+    if (!(next >> v & 1) || orbit_of[v] != v) continue;  // one per orbit
+    prefix.push_back((int8_t)v);
+    const uint32_t now = placed | (1u << v);
+    distinct_orders(p, prefix, now, fixing(group, v), (frontier | nbr_mask(p, v)) & ~now, out);
+    prefix.pop_back();
   }
 }
 
 std::vector<Perm> explore_schedules(const Pattern& p, const std::vector<Perm>& aut) {
   std::vector<Perm> out;
-  Perm sched;
-  explore_rec(p, sched, 0u, aut, 0u, &out);
+  Perm prefix;
+  distinct_orders(p, prefix, 0u, aut, 0u, &out);
   return out;
 }
 
-// Algorithm 1 in the map form of Section 4.3: walking the schedule, every
-// automorphism x of the current group that moves v records "x(v) is bounded
-// by v"; a later v overwrites, which keeps the latest position (Theorem 2).
-// The group then shrinks to the automorphisms fixing v.
+// Restrictions (Algorithm 1) reduced to one bound per loop (Theorem 2), from
+// the stabiliser chain of the schedule: G_0 = Aut and G_{i+1} = the elements
+// of G_i fixing the i-th scheduled vertex v_i.  Every other member u of v_i's
+// orbit under G_i must get a smaller id than v_i; of all such relations on u
+// the one with the latest v_i is kept (it implies the earlier ones), so
+// bound(u) = the position of the last v_i whose G_i-orbit contains u.
 void reduced_bounds(const Pattern& p, const std::vector<Perm>& aut,
                     const int8_t* order, int8_t* bound) {
-  int pos[kMaxK];
-  for (int i = 0; i < p.k; ++i) pos[order[i]] = i;
-  int by[kMaxK];
-  for (int v = 0; v < p.k; ++v) by[v] = -1;
-  std::vector<Perm> group = aut;
+  int last[kMaxK];  // position of the last scheduled vertex bounding u
+  for (int u = 0; u < p.k; ++u) last[u] = -1;
+  std::vector<Perm> chain = aut;
   for (int i = 0; i < p.k; ++i) {
-    int v = order[i];
-    std::vector<Perm> keep;
-    for (const Perm& x : group) {
-      if (x[v] == v)
-        keep.push_back(x);
-      else
-        by[x[v]] = v;
-    }
-    group.swap(keep);
+    const int v = order[i];
+    uint32_t orbit = 0;
+    for (const Perm& g : chain) orbit |= 1u << g[v];
+    for (int u = 0; u < p.k; ++u)
+      if (u != v && (orbit >> u & 1)) last[u] = i;
+    chain = fixing(chain, v);
   }
-  for (int i = 0; i < p.k; ++i) bound[i] = (int8_t)(by[order[i]] < 0 ? -1 : pos[by[order[i]]]);
+  for (int i = 0; i < p.k; ++i) bound[i] = (int8_t)last[order[i]];
 }
 
 // Section 5.4 and the appendix.  In G(n, p) with n = 1000 and average degree
