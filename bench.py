@@ -15,8 +15,15 @@ about 1%.  The full-count time of a pattern is the sum over one cycle of
 slices; it is reported whenever the timed steps cover a cycle.
 
 Other workloads: ``rmat20-cliques`` (K4 and K5 on R-MAT scale 20, one full
-count of each per step) and ``er2000-triangles`` (triangles of
-G(2000, 0.008)).
+count of each per step), ``er2000-triangles`` (triangles of G(2000, 0.008))
+and ``census64-motif4`` (the six connected 4-vertex induced patterns over the
+64 Chung-Lu graphs of the motif batch, one replay of the captured census
+launch per step).
+
+The learned-schedule comparison runs the held-out patterns (6-cycle with a
+chord, K6-e, K7-e) with the analytic and the learned choice on two small
+graphs in full and on the learned-schedule workload's R-MAT 21 and Chung-Lu
+2M graphs over a seeded sample of low-volume roots.
 
 Graph generation and preparation (normalisation, degree reindex, upload)
 happen once before timing and are reported apart, as the paper reports its
@@ -64,6 +71,12 @@ WORKLOADS = {
                                 "(a,b,c,d)=(0.57,0.19,0.19,0.05), seed 2001"),
     "er2000-triangles": dict(graph="er2000", patterns=["triangle"], induced=True, slices=1,
                              desc="triangles, G(2000, 0.008), seed 1001"),
+    # the 21 five-vertex patterns of the same batch are out of reach for the
+    # largest graphs (the 5-star alone enumerates ~4e14 leaf sets)
+    "census64-motif4": dict(graph="census64", patterns=["motif4"], induced=True, slices=1,
+                            desc="census of the 6 connected 4-vertex induced patterns over the "
+                                 "64 Chung-Lu graphs of the motif batch (seeds 4001..4064), "
+                                 "one captured launch"),
 }
 
 
@@ -188,6 +201,118 @@ def learned_vs_analytic(reps=2):
             "cases": cases}
 
 
+def learned_vs_analytic_cfg5(per_stratum=(256, 32), bounds=(1e4, 2e4)):
+    """Learned and analytic schedule choices for the held-out patterns on the
+    learned-schedule workload's own graphs, R-MAT scale 21 (seed 5001) and
+    Chung-Lu n = 2M (exponent 2.2, mean degree 16, seed 5002), over one
+    seeded root sample per graph, the same for both choices: roots of
+    two-hop volume (sum of neighbour degrees) up to 1e4 and in (1e4, 2e4].
+    Heavier roots take 10-90 s each for the 6-cycle with a chord under a
+    good schedule and far longer under a poor one, so full counts and the
+    upper strata are out of reach here; this is a sample."""
+    import numpy as np
+    from paper_1911_12877_amd import gz, learn, synth
+    if not os.path.exists(learn.MODEL_PATH):
+        return None
+    learn.install()
+    cases = []
+    for gname in ("rmat21", "cl2m"):
+        e = synth.config_graph(gname)
+        G = gz.load_edges(*e, flags=gz.GRAPH_PREP_DEVICE)
+        del e
+        r, c, _ = gz.graph_export(G)
+        deg = np.diff(r).astype(np.int64)
+        cs = np.concatenate([[0], np.cumsum(deg[c])])
+        vol = cs[r[1:].astype(np.int64)] - cs[r[:-1].astype(np.int64)]
+        del c, cs
+        rng = np.random.Generator(np.random.PCG64(5150))
+        roots = []
+        for k, (lo, hi) in zip(per_stratum, ((0, bounds[0]), (bounds[0], bounds[1]))):
+            pool = np.nonzero((deg >= 2) & (vol > lo) & (vol <= hi))[0]
+            roots.append(rng.choice(pool, min(k, pool.size), replace=False))
+        roots = np.sort(np.concatenate(roots)).astype(np.int32)
+        for nm, a in learn.held_out_patterns().items():
+            sa = gz.compile_pattern(a, True)
+            sl = gz.compile_pattern_graph(G, a, True, gz.SCHED_LEARNED)
+            log(f"learned vs analytic {gname} {nm}: analytic ...")
+            ca, ma = gz.count_subset(G, sa, roots)
+            log(f"learned vs analytic {gname} {nm}: learned ...")
+            cl, ml = gz.count_subset(G, sl, roots)
+            cases.append({"graph": gname, "pattern": nm, "roots": int(roots.size),
+                          "analytic_ms": round(ma, 3), "learned_ms": round(ml, 3),
+                          "same_schedule": sa.info()["order"] == sl.info()["order"],
+                          "counts_equal": ca == cl})
+            log(f"learned vs analytic {gname} {nm} ({roots.size} roots): "
+                f"{ma:.2f} ms -> {ml:.2f} ms")
+        del G
+    ta = sum(c["analytic_ms"] for c in cases)
+    tl = sum(c["learned_ms"] for c in cases)
+    return {"analytic_ms": round(ta, 3), "learned_ms": round(tl, 3),
+            "speedup": round(ta / tl, 3) if tl > 0 else None,
+            "counts_equal": all(c["counts_equal"] for c in cases),
+            "sample": f"seeded roots of two-hop volume <= {bounds[0]:.0e} ({per_stratum[0]}) "
+                      f"and in ({bounds[0]:.0e}, {bounds[1]:.0e}] ({per_stratum[1]}) per graph",
+            "cases": cases}
+
+
+def census_main(args, wl):
+    """The motif-census workload: one step replays the captured census
+    launch over all (graph, pattern) pairs."""
+    import numpy as np
+    import torch
+    from paper_1911_12877_amd import gz, motifs, synth
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    params = [synth.census_graph_params(i) for i in range(64)]
+    graphs = [gz.load_edges(*synth.config_graph(p), flags=gz.GRAPH_PREP_DEVICE) for p in params]
+    t_prep = time.perf_counter() - t0
+    pats = motifs.connected_patterns(4)
+    scheds = [gz.compile_pattern(a, True) for a in pats]
+    census = gz.Census(graphs, scheds)
+    log(f"64 graphs prepared in {t_prep:.1f}s; {len(pats)} patterns")
+    ref = None
+    for i in range(args.warmup):
+        ref, ms = census.run()
+        log(f"warmup {i}: {ms:.1f} ms")
+    kern = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        counts, ms = census.run()
+        if ref is not None:
+            assert np.array_equal(counts, ref), "census counts changed between replays"
+        ref = counts
+        kern.append(ms)
+        log(f"step {i}: {ms:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total = int(ref.astype(object).sum())
+    alg = None
+    if not args.no_alg_bytes:
+        # the census runs the same loops as single counts: their bytes
+        alg = sum(gz.count_bytes(G, s)[0] for G in graphs for s in scheds)
+    km = float(np.mean(kern))
+    achieved = alg / (km / 1e3) / 1e9 if alg else None
+    out = {
+        "metric": METRIC, "value": round(total * args.steps / wall, 1), "unit": "instances/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "graph": wl["desc"], "graphs": 64,
+                   "patterns": len(pats), "induced": True, "schedule": "analytic",
+                   "step": "one replay of the captured census launch",
+                   "parallelism": "single GPU"},
+        "census_total": total, "prep_s": round(t_prep, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2) if alg else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if alg else None,
+                     "traffic": None, "alg_bytes_per_launch": alg,
+                     "kernel": "k_census<5>", "kernel_ms": round(km, 3)},
+        "cpu_baseline": None, "learned_vs_analytic": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 5 copies of 1 GiB (2^28 int32)
     device to device; each moves 1 GiB in and 1 GiB out of HBM."""
@@ -232,11 +357,15 @@ def main():
               "(the count shards by root; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    wl = WORKLOADS[args.workload]
+    if wl["graph"] == "census64":
+        census_main(args, wl)
+        return
+
     import numpy as np
     import torch
     from paper_1911_12877_amd import gz, motifs, synth
 
-    wl = WORKLOADS[args.workload]
     S = max(1, args.slices or wl["slices"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -365,6 +494,7 @@ def main():
                "one_core": {"value": round(v1, 1), "seconds": round(dt1, 2)}}
 
     lva = None if args.no_learned else learned_vs_analytic()
+    lva5 = None if args.no_learned else learned_vs_analytic_cfg5()
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "instances/s",
@@ -383,6 +513,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned_vs_analytic": lva,
+        "learned_vs_analytic_rmat21_cl2m": lva5,
     }
     print(json.dumps(out), flush=True)
 
