@@ -370,14 +370,23 @@ gz_status gz_schedule_features(const gz_graph* g, const uint8_t* adj, int32_t k,
                                int32_t induced, const int8_t* order,
                                float* out);
 
+/* The last GZ_GRAPH_STATS features of a row are the graph's statistics. */
+#define GZ_GRAPH_STATS 8
+
 /* Install (copy) a model for GZ_SCHED_LEARNED, process-wide; params NULL
- * removes it.  D must be GZ_FEATURES, 1 <= H <= 1024.  margin (log10 of
- * time, >= 0): a learned choice replaces the analytic model's pick only
- * when the network predicts it faster by more than margin.  k_max (2..8):
- * the largest pattern in the model's training corpus; larger patterns keep
- * the analytic pick. */
+ * removes it.  D must be GZ_FEATURES, 1 <= H <= 1024.  The learned choice
+ * keeps the analytic model's pick unless the network is on known ground
+ * and sure:
+ *  - margin (log10 of time, >= 0): the network must predict its choice
+ *    faster than the analytic pick by more than this;
+ *  - k_max (2..8): the largest pattern in its training corpus; larger
+ *    patterns keep the analytic pick;
+ *  - graph_range (2 x GZ_GRAPH_STATS floats, or NULL for no limit): the
+ *    smallest then the largest value of each graph statistic over the
+ *    corpus; a graph outside that range (by more than 0.05) keeps the
+ *    analytic pick. */
 gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H, float margin,
-                            int32_t k_max);
+                            int32_t k_max, const float* graph_range);
 
 /* gz_compile_pattern with the graph the schedule will run on.  With
  * GZ_SCHED_LEARNED and an installed model the distinct schedule of lowest

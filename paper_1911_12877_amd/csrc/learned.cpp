@@ -30,6 +30,11 @@ std::vector<float> g_model;
 int g_model_h = 0;
 float g_model_margin = 0.0f;
 int32_t g_model_kmax = 0;
+// range of the graph statistics (the last GZ_GRAPH_STATS features) over the
+// model's training corpus; graphs outside it keep the analytic pick
+bool g_model_ranged = false;
+float g_model_gmin[GZ_GRAPH_STATS], g_model_gmax[GZ_GRAPH_STATS];
+constexpr float kRangeSlack = 0.05f;  // in the features' scaled-log units
 
 double lg(double x) { return std::log10(std::max(x, 1e-30)); }
 float clampf(double x, double lo, double hi) { return (float)std::min(hi, std::max(lo, x)); }
@@ -154,13 +159,14 @@ gz_status gz_schedule_features(const gz_graph* g, const uint8_t* adj, int32_t k,
 }
 
 gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H, float margin,
-                            int32_t k_max) {
+                            int32_t k_max, const float* graph_range) {
   std::lock_guard<std::mutex> lock(g_model_mu);
   if (!params) {
     g_model.clear();
     g_model_h = 0;
     g_model_margin = 0.0f;
     g_model_kmax = 0;
+    g_model_ranged = false;
     return GZ_OK;
   }
   if (D != GZ_FEATURES || H < 1 || H > 1024 || !(margin >= 0.0f && margin < 100.0f) ||
@@ -173,6 +179,11 @@ gz_status gz_set_cost_model(const float* params, int32_t D, int32_t H, float mar
   g_model_h = H;
   g_model_margin = margin;
   g_model_kmax = k_max;
+  g_model_ranged = graph_range != nullptr;
+  for (int i = 0; i < GZ_GRAPH_STATS && graph_range; ++i) {
+    g_model_gmin[i] = graph_range[i];
+    g_model_gmax[i] = graph_range[GZ_GRAPH_STATS + i];
+  }
   return GZ_OK;
 }
 
@@ -188,12 +199,17 @@ gz_status gz_compile_pattern_graph(const gz_graph* g, const uint8_t* adj, int32_
   int H = 0;
   float margin = 0.0f;
   int32_t kmax = 0;
+  bool ranged = false;
+  float gmin[GZ_GRAPH_STATS], gmax[GZ_GRAPH_STATS];
   {
     std::lock_guard<std::mutex> lock(g_model_mu);
     model = g_model;
     H = g_model_h;
     margin = g_model_margin;
     kmax = g_model_kmax;
+    ranged = g_model_ranged;
+    std::copy(g_model_gmin, g_model_gmin + GZ_GRAPH_STATS, gmin);
+    std::copy(g_model_gmax, g_model_gmax + GZ_GRAPH_STATS, gmax);
   }
   const uint32_t rest = flags & ~(uint32_t)GZ_SCHED_LEARNED;
   // no model, or a pattern larger than any in its corpus (features of loops
@@ -206,6 +222,14 @@ gz_status gz_compile_pattern_graph(const gz_graph* g, const uint8_t* adj, int32_
   std::vector<float> X((size_t)n * GZ_FEATURES);
   for (int i = 0; i < n; ++i)
     schedule_features(g, p, aut, induced != 0, ds[i].data(), X.data() + (size_t)i * GZ_FEATURES);
+  // a graph whose statistics lie outside the corpus's range: the network
+  // would extrapolate, so the analytic model decides
+  if (ranged && n > 0) {
+    const float* st = X.data() + GZ_FEATURES - GZ_GRAPH_STATS;
+    for (int i = 0; i < GZ_GRAPH_STATS; ++i)
+      if (st[i] < gmin[i] - kRangeSlack || st[i] > gmax[i] + kRangeSlack)
+        return build_schedule_for(p, induced, rest, nullptr, out);
+  }
   std::vector<float> y;
   gz_status rc = predict(model, H, X, n, &y);
   if (rc) return rc;

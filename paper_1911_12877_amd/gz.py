@@ -80,7 +80,7 @@ def _load():
         "gz_census_tune": [P, P, P],
         "gz_prepare_edges": [P, P, i64, i32, u32, P, P, P, P, P],
         "gz_schedule_features": [P, P, i32, i32, P, P],
-        "gz_set_cost_model": [P, i32, i32, ctypes.c_float, i32],
+        "gz_set_cost_model": [P, i32, i32, ctypes.c_float, i32, P],
         "gz_compile_pattern_graph": [P, P, i32, i32, u32, P],
         "gz_mlp_forward": [P, P, i32, i32, i32, i32, P, P],
         "gz_mlp_loss_grad": [P, P, P, i32, i32, i32, P, P, P],
@@ -406,16 +406,25 @@ def schedule_features(g: Graph, adj, order, induced=True):
     return out
 
 
-def set_cost_model(params, H=None, margin=0.0, k_max=8):
+GRAPH_STATS = 8
+
+
+def set_cost_model(params, H=None, margin=0.0, k_max=8, graph_range=None):
     """gz_set_cost_model: install FP32 parameters (None removes the model);
     margin: the predicted gain (log10 time) a learned choice must exceed;
-    k_max: the largest pattern size the model was trained on."""
+    k_max: the largest pattern size the model was trained on; graph_range:
+    (min, max) arrays of the graph statistics over its corpus, or None."""
     if params is None:
-        _check(_load().gz_set_cost_model(None, FEATURES, 1, ctypes.c_float(0.0), 8))
+        _check(_load().gz_set_cost_model(None, FEATURES, 1, ctypes.c_float(0.0), 8, None))
         return
     p = _np(params, np.float32)
+    rng = None
+    if graph_range is not None:
+        rng = np.concatenate([np.asarray(graph_range[0], np.float32).ravel(),
+                              np.asarray(graph_range[1], np.float32).ravel()])
+        assert rng.size == 2 * GRAPH_STATS
     _check(_load().gz_set_cost_model(p.ctypes.data, FEATURES, H, ctypes.c_float(margin),
-                                     int(k_max)))
+                                     int(k_max), rng.ctypes.data if rng is not None else None))
 
 
 def compile_pattern_graph(g: Graph, adj, induced=True, flags=SCHED_LEARNED) -> Schedule:

@@ -13,9 +13,10 @@ chord, K6 minus an edge, K7 minus an edge) are never in the corpus.
 
 A learned choice replaces the analytic model's pick only when the network
 predicts it faster by more than twice its validation error (group-wise
-cross-validation over the corpus, stored with the weights as `margin`), and
-only for patterns no larger than the corpus's (`k_max`): the features of
-further loops were never seen in training.
+cross-validation over the corpus, stored with the weights as `margin`), only
+for patterns no larger than the corpus's (`k_max`), and only on graphs whose
+statistics lie within the corpus's range (`graph_min`, `graph_max`): the
+network was never trained beyond them.
 
 Command line (GPU):  python -m paper_1911_12877_amd.learn collect OUT.npz
                      python -m paper_1911_12877_amd.learn train IN.npz [MODEL.npz]
@@ -276,25 +277,37 @@ def corpus_k_max(X):
 MARGIN_SIGMAS = 2.0
 
 
-def save(params, H, path=MODEL_PATH, margin=0.0, k_max=8):
+def corpus_graph_range(X):
+    """(min, max) of the graph statistics (the last GRAPH_STATS features)
+    over the corpus rows."""
+    st = np.asarray(X, dtype=np.float32)[:, -gz.GRAPH_STATS:]
+    return st.min(axis=0), st.max(axis=0)
+
+
+def save(params, H, path=MODEL_PATH, margin=0.0, k_max=8, graph_range=None):
     os.makedirs(os.path.dirname(path), exist_ok=True)
+    extra = {}
+    if graph_range is not None:
+        extra = dict(graph_min=np.asarray(graph_range[0], np.float32),
+                     graph_max=np.asarray(graph_range[1], np.float32))
     np.savez(path, params=np.asarray(params, dtype=np.float32), H=np.int32(H),
-             D=np.int32(gz.FEATURES), margin=np.float32(margin), k_max=np.int32(k_max))
+             D=np.int32(gz.FEATURES), margin=np.float32(margin), k_max=np.int32(k_max), **extra)
 
 
 def load(path=MODEL_PATH):
-    """(params, H, validation error, k_max); 0 and 8 for a file written
-    without them."""
+    """(params, H, validation error, k_max, graph range or None); 0, 8 and
+    None for a file written without them."""
     z = np.load(path)
     margin = float(z["margin"]) if "margin" in z.files else 0.0
     k_max = int(z["k_max"]) if "k_max" in z.files else 8
-    return z["params"].astype(np.float32), int(z["H"]), margin, k_max
+    rng = (z["graph_min"], z["graph_max"]) if "graph_min" in z.files else None
+    return z["params"].astype(np.float32), int(z["H"]), margin, k_max, rng
 
 
 def install(path=MODEL_PATH):
     """Install the bundled (or given) model for GZ_SCHED_LEARNED."""
-    params, H, err, k_max = load(path)
-    gz.set_cost_model(params, H, MARGIN_SIGMAS * err, k_max)
+    params, H, err, k_max, rng = load(path)
+    gz.set_cost_model(params, H, MARGIN_SIGMAS * err, k_max, rng)
     return params, H
 
 
@@ -307,7 +320,7 @@ def main(argv):
         P, losses = train(X, centred(y, grp), log=print)
         margin = cv_margin(X, y, grp, log=print)
         out = argv[2] if len(argv) > 2 else MODEL_PATH
-        save(P, H_DEFAULT, out, margin, corpus_k_max(X))
+        save(P, H_DEFAULT, out, margin, corpus_k_max(X), corpus_graph_range(X))
         print(f"saved {out}; final loss {losses[-1]:.4f}, validation error {margin:.4f}")
     elif len(argv) >= 2 and argv[0] == "margin":
         # the validation error of a saved model's training recipe, stored
@@ -315,9 +328,9 @@ def main(argv):
         z = np.load(argv[1])
         X, y, grp = z["X"], z["y"], z["group"]
         out = argv[2] if len(argv) > 2 else MODEL_PATH
-        params, H, _, _ = load(out)
+        params, H, _, _, _ = load(out)
         margin = cv_margin(X, y, grp, log=print)
-        save(params, H, out, margin, corpus_k_max(X))
+        save(params, H, out, margin, corpus_k_max(X), corpus_graph_range(X))
         print(f"saved {out}; validation error {margin:.4f}, k_max {corpus_k_max(X)}")
     else:
         print(__doc__)
