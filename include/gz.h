@@ -185,8 +185,8 @@ void gz_free_schedule(gz_schedule* s);
  * How the count is evaluated - never its value - can be steered by
  * environment variables read at every call (decimal integers; invalid or
  * out-of-range values are ignored):
- *  - GZ_SPLIT_MIN_LEN (>= 0, default 2048) and GZ_SPLIT_CAP (1..2^26,
- *    default 2^20): patterns of k >= 4 on the generic loops run in two
+ *  - GZ_SPLIT_MIN_LEN (>= 0, default 64) and GZ_SPLIT_CAP (1..2^26,
+ *    default 2^22): patterns of k >= 4 on the generic loops run in two
  *    phases; prefixes whose loop base is longer than the threshold are
  *    recorded by the first launch (up to the capacity; later ones are
  *    expanded in place) and expanded in 256-element pieces by a second, the

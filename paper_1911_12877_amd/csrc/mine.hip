@@ -1637,7 +1637,7 @@ int split_min_len() {
     const long v = std::strtol(e, &end, 10);
     if (end && *end == '\0' && v >= 0 && v <= INT32_MAX) return (int)v;
   }
-  return 8 * dev::CH;
+  return 64;
 }
 
 // Capacity of the record list (GZ_SPLIT_CAP overrides); prefixes met once
@@ -1649,7 +1649,7 @@ long long split_cap() {
     const long long v = std::strtoll(e, &end, 10);
     if (end && *end == '\0' && v >= 1 && v <= (1ll << 26)) return v;
   }
-  return 1ll << 20;
+  return 1ll << 22;
 }
 
 // Vertices of at least this degree get a neighbour bitmap (GZ_HUB_MIN_DEG
