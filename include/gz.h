@@ -204,6 +204,14 @@ void gz_free_schedule(gz_schedule* s);
  *    negative lists when that costs less than GZ_IE_RATIO/8 of walking its
  *    shortest positive list.  GZ_IE_FORCE=1 makes every item with negative
  *    lists take inclusion-exclusion.
+ *  - GZ_SWEEP_MIN (>= 0, default 16384) and GZ_SWEEP_IE (>= 0, default 2):
+ *    when every positive list of the loops before an item's is a hub's, a
+ *    group of last-loop items that walk their own rows is swept instead:
+ *    those loops' lists become one bit mask per block of 2^15 vertex ids in
+ *    LDS, and each item row entry costs one read of the row and one of the
+ *    mask.  A group is swept when its rows total at least GZ_SWEEP_MIN
+ *    entries (0: never); an item keeps inclusion-exclusion when that walks
+ *    under 1/GZ_SWEEP_IE of its row.
  *  - GZ_CLIQUE_MAX_LO (0..1024, default 1024): clique schedules run on
  *    per-root bit rows (see gz_count_ops) for roots with at most this many
  *    first-loop candidates; roots with more take the generic loops.
@@ -272,8 +280,13 @@ gz_status gz_count_subset(const gz_graph* g, const gz_schedule* s,
  * 4 bytes per element of each neighbour list the loop's set expression
  * reads (pattern-edge lists, plus pattern-non-edge lists when induced), cut
  * at the loop's restriction bound (Section 6, second technique), plus 8 bytes
- * per list for its row offsets.  Runs an instrumented (slower) pass; the
- * count of that pass is returned too.
+ * per list for its row offsets.  Loop i is evaluated once per iteration of
+ * loop i-1, along which only the list of v_{i-1} changes: that list counts
+ * per evaluation, the others once per execution of loop i-1 (at its last
+ * iteration's cut, the longest).  A loop that extends loop i-1's candidate
+ * set reads that set's elements instead of the lists it shares with it.
+ * Runs an instrumented (slower) pass; the count of that pass is returned
+ * too.
  */
 gz_status gz_count_bytes(const gz_graph* g, const gz_schedule* s,
                          void* hip_stream, uint64_t* out_bytes,

@@ -64,6 +64,12 @@ struct Plan {
   // elements times probes per element) is below ie_ratio / 8 of the direct
   // evaluation's
   int32_t ie_ratio = 12;
+  // last loop: a group of items whose own rows are walked is swept (one LDS
+  // mask per block of vertex ids for the earlier loops' lists) when those
+  // walks total at least sweep_min entries (0: never); an item keeps
+  // inclusion-exclusion when that walks under 1 / sweep_ie of its row
+  int32_t sweep_min = 0;
+  int32_t sweep_ie = 2;
 };
 
 // ---------------------------------------------------------------- patterns

@@ -47,6 +47,20 @@ constexpr int SRC_SLOT = 8;
 constexpr int WALK_TILE = 4 * WAVE;
 template <int K>
 constexpr int walk_tile() { return K <= 4 ? WALK_TILE : (K <= 5 ? 2 * WAVE : WAVE); }
+// last-loop sweep: an LDS mask covers 2^SW_SHIFT consecutive vertex ids at a
+// time; the kernels of patterns up to SW_KMAX vertices carry it
+constexpr int SW_SHIFT = 15;
+constexpr int SW_WORDS = (1 << SW_SHIFT) / 32;
+constexpr int SW_KMAX = 5;
+template <int K>
+constexpr int sweep_words() { return K <= SW_KMAX ? SW_WORDS : 1; }
+// Waves per SIMD the generic kernels are compiled for (1: the compiler's
+// choice).  Their loops wait on scattered loads, so for 4-vertex patterns
+// more resident waves beat the few registers spilled to reach them.
+template <int K>
+constexpr int mine_waves() { return K == 4 ? 4 : 1; }
+template <int K>
+constexpr int heavy_waves() { return K == 4 ? 7 : 1; }
 
 struct Graph {
   const int32_t* __restrict__ rowptr;
@@ -93,15 +107,23 @@ struct WaveMem {
   static constexpr int NSET = K >= 4 ? K - 3 : 1;
   int32_t set[NSET][CH];
   int32_t set_len[NSET];
-  int32_t it_u[WAVE];
-  int32_t it_pref[WAVE];
-  int32_t it_bstart[WAVE];
-  int32_t it_slot[WAVE];
-  int32_t it_srclen[WAVE];
-  int32_t it_urs[WAVE];
-  int32_t it_urd[WAVE];
-  int32_t it_ie[WAVE];
-  int32_t win[WALK_TILE];  // a window of a list being merged (long last-loop walks)
+  // The last loop's phases use disjoint LDS: a group's items while their
+  // pairs are walked, a merge window during long walks, the sweep mask
+  union {
+    struct {
+      int32_t it_u[WAVE];
+      int32_t it_pref[WAVE];
+      int32_t it_bstart[WAVE];
+      int32_t it_slot[WAVE];
+      int32_t it_srclen[WAVE];
+      int32_t it_urs[WAVE];
+      int32_t it_urd[WAVE];
+      int32_t it_ie[WAVE];
+      int32_t win[WALK_TILE];  // a window of a list being merged (long walks)
+    };
+    // one block of the sweep mask: bit x of word w is vertex id base + 32w + x
+    uint32_t mask[sweep_words<K>()];
+  };
   // the lists of the long walk being counted: start in col, bounded length
   // and owner vertex, by list index (see Lists)
   int32_t ls_start[K];
@@ -275,6 +297,123 @@ __device__ long long wave_walk(const Graph& g, WaveMem<K>& M, const int32_t* W, 
   return cnt;
 }
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t x) {
+#pragma unroll
+  for (int d = WAVE / 2; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, WAVE));
+  return uni(x);
+}
+
+// Last-loop sweep over one group of items, one per lane (`mine` where the
+// lane's item takes part).  Each item walks its own row g.col[start ..
+// start + len) (already cut to the loop's bound), and an entry x counts when
+// it lies in every list of `pm`, in no list of `nm` (lists of the loops
+// before the item's) and differs from the vertices of the loops in `em`.
+// Those tests do not depend on the item, so they are folded into one bit
+// mask over vertex ids, built in LDS a block of 2^SW_SHIFT ids at a time:
+// AND of the positive lists' hub bitmaps, AND-NOT of the negative lists'
+// (a negative list without a bitmap clears its entries' bits), the `em`
+// vertices cleared.  Every entry then costs one coalesced read of its row
+// and one LDS read, instead of one scattered bitmap probe per list.  Blocks
+// no item reaches are skipped.  Within a block the items' runs are read a
+// tile of 64 consecutive entries at a time, up to SW_TILES tiles of
+// different items in flight.  The result is wave-uniform.
+constexpr int SW_TILES = 4;
+template <int K>
+__device__ long long sweep_items(const Graph& g, WaveMem<K>& M, const int32_t (&v)[K],
+                                 const int32_t (&rs)[K], const int32_t (&rd)[K], uint32_t pm,
+                                 uint32_t nm, uint32_t em, bool mine, int32_t start,
+                                 int32_t len) {
+  const int lane = lane_id();
+  int c = 0;  // the lane's item: entries before c are done
+  // its next entry, or a placeholder below the block's end while a whole
+  // tile of the item fell in the current block
+  int32_t nx = (mine && len > 0) ? g.col[start] : INF;
+  int pc[K];  // cursors of the negative lists without a bitmap
+#pragma unroll
+  for (int j = 0; j < K; ++j) pc[j] = 0;
+  long long cnt = 0;
+  for (;;) {
+    const int32_t m0 = wave_min_i32(nx);
+    if (m0 == INF) break;
+    const int32_t base = m0 & ~((1 << SW_SHIFT) - 1);
+    const long long top = (long long)base + (1 << SW_SHIFT);
+    const long long w0 = base >> 5;
+#pragma unroll 2
+    for (int w = lane; w < SW_WORDS; w += WAVE) {
+      const bool in_row = w0 + w < g.hub_words;
+      uint32_t m = ~0u;
+      if (in_row) {
+#pragma unroll
+        for (int j = 0; j < K - 2; ++j) {
+          if ((pm >> j) & 1u) m &= g.hub[(long long)v[j] * g.hub_words + w0 + w];
+          if (((nm >> j) & 1u) && v[j] < g.n_hub) m &= ~g.hub[(long long)v[j] * g.hub_words + w0 + w];
+        }
+      } else if (pm != 0u) {
+        m = 0u;  // ids past the graph's last vertex
+      }
+      M.mask[w] = m;
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < K - 2; ++j) {
+      if (!((nm >> j) & 1u) || v[j] < g.n_hub) continue;
+      for (;;) {
+        const int q = pc[j] + lane;
+        const int32_t y = q < rd[j] ? g.col[rs[j] + q] : INF;
+        const bool below = y < top;
+        if (below && y >= base) atomicAnd(&M.mask[(y - base) >> 5], ~(1u << (y & 31)));
+        const int adv = __popcll(__ballot(below));
+        pc[j] += adv;
+        if (adv < WAVE) break;
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < K - 2; ++j)
+        if (((em >> j) & 1u) && v[j] >= base && v[j] < top)
+          atomicAnd(&M.mask[(v[j] - base) >> 5], ~(1u << (v[j] & 31)));
+    }
+    wave_sync();
+    for (;;) {
+      unsigned long long act = __ballot(nx < top);
+      if (act == 0ull) break;
+      int it[SW_TILES];
+      int32_t x[SW_TILES];
+#pragma unroll
+      for (int u = 0; u < SW_TILES; ++u) {
+        it[u] = -1;
+        x[u] = INF;
+        if (act != 0ull) {
+          it[u] = __ffsll((long long)act) - 1;
+          act &= act - 1;
+          const int ci = __builtin_amdgcn_readlane(c, it[u]);
+          const int li = __builtin_amdgcn_readlane(len, it[u]);
+          const int32_t si = __builtin_amdgcn_readlane(start, it[u]);
+          const int q = ci + lane;
+          x[u] = q < li ? g.col[si + q] : INF;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SW_TILES; ++u) {
+        if (it[u] < 0) continue;
+        const bool in = x[u] < top;
+        const int wi = in ? (x[u] - base) >> 5 : 0;
+        const bool ok = in && ((M.mask[wi] >> (x[u] & 31)) & 1u);
+        cnt += __popcll(__ballot(ok));
+        const int adv = __popcll(__ballot(in));
+        // the item's first entry past the block (INF past its row's end)
+        const int32_t after = adv < WAVE ? __builtin_amdgcn_readlane(x[u], adv) : 0;
+        if (lane == it[u]) {
+          c += adv;
+          nx = adv < WAVE ? after : (c < len ? base : INF);
+        }
+      }
+    }
+    wave_sync();
+  }
+  return cnt;
+}
+
 // Count of the last loop for the items of one chunk of loop K-2.
 //
 // Each item's candidates are x < B in every positive list (the loop's
@@ -298,7 +437,7 @@ template <int K, bool INSTR, bool IE, bool BIG>
 __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                            const int32_t (&v)[K], const int32_t (&rs)[K],
                            const int32_t (&rd)[K], uint32_t complete,
-                           const int32_t* items, int n_items, int item_base, Acc& acc) {
+                           const int32_t* items, int n_items, Acc& acc) {
   constexpr int J = K - 2;  // loop of the items
   const Level L = plan.lv[K - 1];
   const int lane = lane_id();
@@ -312,6 +451,24 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
   const int src_full = use_src ? M.set_len[src_idx] : 0;
   const int n_pos = __popc(pos) + (use_src ? 1 : 0);
   const int m_neg = __popc(neg);
+  // items walking their own row may be swept instead (sweep_items): the
+  // lists of the earlier loops must then be tests of the entry alone - every
+  // positive one a hub's bitmap
+  bool sweep_on = false;
+  uint32_t sw_pm = 0u, sw_nm = 0u, sw_em = 0u;
+  if constexpr (BIG && !INSTR && K <= SW_KMAX) {
+    const uint32_t early = (1u << J) - 1u;
+    if (plan.sweep_min > 0 && !plan.ie_force && !use_src && ((pos >> J) & 1u) &&
+        !((neg >> J) & 1u)) {
+      sw_pm = pos & early;
+      sw_nm = neg & early;
+      sw_em = L.excl & early;
+      sweep_on = true;
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        if (((sw_pm >> j) & 1u) && v[j] >= g.n_hub) sweep_on = false;
+    }
+  }
 
   // bounded lengths of the rows of loops j < J (exact when the bound does
   // not depend on the item; otherwise the full row, an upper bound that is
@@ -363,17 +520,13 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         }
       }
       if constexpr (INSTR) {
-        // extension of the enclosing set: its elements below u (the item's
-        // rank) plus the added lists; otherwise every list of the loop
+        // the item's own list (the lists of the earlier loops, and the
+        // enclosing set an extension reads, stay the same along the items'
+        // loop: invariant_bytes, once per execution of that loop)
         const bool ext = (L.acct & 0x80u) != 0;
         const uint32_t all = ext ? (L.acct & 0x7fu) : (uint32_t)(L.isect | L.sub);
-        unsigned long long b = ext ? 4ull * (unsigned)(item_base + t) : 0ull;
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-          if ((all >> j) & 1u)
-            b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
-        if ((all >> J) & 1u) b += 4ull * (unsigned)bounded_len(g, u, urs, urd, B, item_bound) + 8ull;
-        acc.bytes += b;
+        if ((all >> J) & 1u)
+          acc.bytes += 4ull * (unsigned)bounded_len(g, u, urs, urd, B, item_bound) + 8ull;
       } else if (IE && m_neg > 0 && (plan.ie_force || blen > IE_MIN || BIG)) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -405,9 +558,25 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     } else {
       blen = 0;
     }
+    // swept items: walking their own row, unless inclusion-exclusion walks
+    // less than 1 / sweep_ie of it; a group sweeps when the swept walks
+    // total at least sweep_min entries (the mask's cost is per block)
+    bool sw = false;
+    if constexpr (BIG && !INSTR && K <= SW_KMAX) {
+      if (sweep_on) {
+        const long long ie_all = (n_pos > 1 ? blen : 0) + ie_walk;
+        sw = valid && slot == J && blen > 0 &&
+             (!ie || (long long)plan.sweep_ie * ie_all >= (long long)blen);
+        long long tot = sw ? blen : 0;
+#pragma unroll
+        for (int d = WAVE / 2; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, WAVE);
+        if (tot < plan.sweep_min) sw = false;
+        if (sw) ie = false;
+      }
+    }
     // items with a long walk are counted by the whole wave below, 64
     // consecutive elements at a time; the rest share the wave pair by pair
-    const long long walk = ie ? (n_pos > 1 ? blen : 0) + ie_walk : blen;
+    const long long walk = ie ? (n_pos > 1 ? blen : 0) + ie_walk : (sw ? 0 : blen);
     const bool lng = BIG && !INSTR && valid && walk >= plan.long_min;
     const bool any_ie = IE && __ballot(ie && !lng) != 0ull;
     const uint32_t n_terms = any_ie ? (1u << m_neg) : 1u;
@@ -431,7 +600,7 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
       if (lng) {
         elen = 0;
       } else if (!ie) {
-        elen = (T == 0) ? blen : 0;
+        elen = (T == 0 && !sw) ? blen : 0;
       } else if (T == 0) {
         if (n_pos == 1) local += blen;  // a single bounded list: its length
         else elen = blen;
@@ -557,6 +726,12 @@ __device__ void last_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
         wave_sync();  // the item's lists stay in LDS until its terms are done
       }
     }
+    if constexpr (BIG && !INSTR && K <= SW_KMAX) {
+      if (sweep_on && __ballot(sw) != 0ull) {
+        const long long c = sweep_items<K>(g, M, v, rs, rd, sw_pm, sw_nm, sw_em, sw, urs, blen);
+        if (lane == 0) local += c;
+      }
+    }
     if (ie) {
       // inclusion-exclusion counted the excl vertices that pass every test
       for (int j = 0; j <= J; ++j) {
@@ -600,24 +775,42 @@ struct Split {
   int32_t r;                     // current root slot
 };
 
+// Algorithmic bytes of loop I's set expression that do not change along the
+// loop above it (loop I-1): the lists of the loops before I-1 or, when loop
+// I extends loop I-1's set, that set's elements below v[I-1] and the lists it
+// adds before I-1.  They are counted once per execution of loop I-1, at its
+// last iteration (v[I-1] its last element, of rank `rank_last`), whose cut
+// is the longest.  The list of v[I-1] itself is counted per iteration.
+template <int K, int I>
+__device__ unsigned long long invariant_bytes(const Graph& g, const Level& L,
+                                              const int32_t (&v)[K], const int32_t (&rs)[K],
+                                              const int32_t (&rd)[K], int rank_last) {
+  const int32_t B = L.bound >= 0 ? v[L.bound] : INF;
+  const bool ext = (L.acct & 0x80u) != 0;
+  const uint32_t all = ext ? (L.acct & 0x7fu) : (uint32_t)(L.isect | L.sub);
+  unsigned long long b = ext ? 4ull * (unsigned)rank_last : 0ull;
+#pragma unroll
+  for (int j = 0; j < I - 1; ++j)
+    if ((all >> j) & 1u)
+      b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
+  return b;
+}
+
 template <int K, int I, bool INSTR, bool IE, bool BIG>
 __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
                           int32_t (&v)[K], int32_t (&rs)[K], int32_t (&rd)[K],
-                          uint32_t complete, int rank_prev, Acc& acc, const Split& sp,
+                          uint32_t complete, Acc& acc, const Split& sp,
                           int c_lo = 0, int c_hi = INF) {
   const Level L = plan.lv[I];
   const int lane = lane_id();
   const int32_t B = L.bound >= 0 ? v[L.bound] : INF;
   if (INSTR && lane == 0) {
-    // rank_prev: position of v[I-1] in the enclosing loop's set
+    // the list of v[I-1], per evaluation (the rest: invariant_bytes)
     const bool ext = (L.acct & 0x80u) != 0;
     const uint32_t all = ext ? (L.acct & 0x7fu) : (uint32_t)(L.isect | L.sub);
-    unsigned long long b = ext ? 4ull * (unsigned)rank_prev : 0ull;
-#pragma unroll
-    for (int j = 0; j < I; ++j)
-      if ((all >> j) & 1u)
-        b += 4ull * (unsigned)bounded_len(g, v[j], rs[j], rd[j], B, L.bound == j) + 8ull;
-    acc.bytes += b;
+    if ((all >> (I - 1)) & 1u)
+      acc.bytes +=
+          4ull * (unsigned)bounded_len(g, v[I - 1], rs[I - 1], rd[I - 1], B, L.bound == I - 1) + 8ull;
   }
   const bool use_src = L.src >= 0 && ((complete >> L.src) & 1u);
   const int src_idx = use_src ? L.src - 2 : 0;
@@ -663,6 +856,7 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
   const int c_end = min(blen, c_hi);
   if (blen <= CH && c_lo == 0) mine |= 1u << I;
   int cum = 0;  // survivors of earlier chunks: rank of this chunk's first element
+  int32_t last = 0;  // the last survivor so far
   for (int c0 = c_lo; c0 < c_end; c0 += CH) {
     const int c1 = min(c_end, c0 + CH);
     int nout = 0;
@@ -687,18 +881,23 @@ __device__ void mat_level(const Graph& g, const Plan& plan, WaveMem<K>& M,
     }
     if (lane == 0) M.set_len[I - 2] = nout;
     wave_sync();
+    if (INSTR && nout > 0) last = uni(out[nout - 1]);
     if constexpr (I == K - 2) {
-      last_level<K, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, out, nout, cum, acc);
+      last_level<K, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, out, nout, acc);
     } else {
       for (int t = 0; t < nout; ++t) {
         v[I] = uni(out[t]);
         rs[I] = uni(g.rowptr[v[I]]);
         rd[I] = uni(g.rowptr[v[I] + 1]) - rs[I];
-        mat_level<K, I + 1, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, cum + t, acc, sp);
+        mat_level<K, I + 1, INSTR, IE, BIG>(g, plan, M, v, rs, rd, mine, acc, sp);
       }
     }
     cum += nout;
     wave_sync();
+  }
+  if (INSTR && cum > 0) {
+    v[I] = last;
+    if (lane == 0) acc.bytes += invariant_bytes<K, I + 1>(g, plan.lv[I + 1], v, rs, rd, cum - 1);
   }
 }
 
@@ -730,7 +929,8 @@ __device__ __forceinline__ void wave_sum_u128(unsigned long long x,
 }
 
 template <int K, bool PER_ROOT, bool INSTR, bool IE>
-__global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out o) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mine_waves<K>())))
+void k_mine(Graph g, Plan plan, Tasks T, Out o) {
   __shared__ WaveMem<K> mem[WPB];
   WaveMem<K>& M = mem[threadIdx.x / WAVE];
   const int lane = lane_id();
@@ -767,14 +967,21 @@ __global__ __launch_bounds__(BLOCK) void k_mine(Graph g, Plan plan, Tasks T, Out
         if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
       } else if constexpr (K == 3) {
         last_level<K, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin,
-                             end - begin, begin, acc);
+                                           end - begin, acc);
       } else {
         for (int32_t i = begin; i < end; ++i) {
           v[1] = uni(g.col[rs0 + i]);
           rs[1] = uni(g.rowptr[v[1]]);
           rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
           const Split sp{T.heavy, o.acc + 6, T.heavy_cap, T.heavy_min, (int32_t)slot};
-          mat_level<K, 2, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, i, acc, sp);
+          mat_level<K, 2, INSTR, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, acc, sp);
+        }
+      }
+      if constexpr (INSTR && K >= 3) {
+        // loop 2's lists of v0: once per root, with the root's last loop-1 element
+        if (end == len1 && len1 > 0) {
+          v[1] = uni(g.col[rs0 + len1 - 1]);
+          if (lane == 0) acc.bytes += invariant_bytes<K, 2>(g, plan.lv[2], v, rs, rd, len1 - 1);
         }
       }
       if constexpr (PER_ROOT) {
@@ -1300,7 +1507,8 @@ __global__ __launch_bounds__(CBLOCK) void k_clique_block(Graph g, RootList L, Ou
 // loops below take their operands from the neighbour lists.  One launch per
 // depth keeps one chain of loops per kernel.
 template <int K, bool PER_ROOT, int LV, bool IE>
-__global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const HeavyItem* items,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(heavy_waves<K>())))
+void k_mine_heavy(Graph g, Plan plan, const HeavyItem* items,
                                                       const long long* piece_prefix,
                                                       long long n_items,
                                                       unsigned long long* queue, Out o) {
@@ -1330,7 +1538,7 @@ __global__ __launch_bounds__(BLOCK) void k_mine_heavy(Graph g, Plan plan, const 
       rd[j] = (j < LV) ? uni(g.rowptr[v[j] + 1]) - rs[j] : 0;
     }
     const int c0 = (int)(t - piece_prefix[h]) * CH;
-    mat_level<K, LV, false, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, 0, acc, none, c0, c0 + CH);
+    mat_level<K, LV, false, IE, (K <= 7)>(g, plan, M, v, rs, rd, 0u, acc, none, c0, c0 + CH);
     if constexpr (PER_ROOT) {
       unsigned long long l, hh;
       wave_sum_u128(acc.cnt, &l, &hh);
@@ -1423,14 +1631,14 @@ __device__ void census_task(const Graph& g, const Plan& plan, WaveMem<K>& M,
     if (lane == 0) acc.cnt += (unsigned long long)(end - begin);
   } else if constexpr (K == 3) {
     last_level<K, false, false, false>(g, plan, M, v, rs, rd, 0u, g.col + rs0 + begin, end - begin,
-                                     begin, acc);
+                                       acc);
   } else {
     for (int32_t i = begin; i < end; ++i) {
       v[1] = uni(g.col[rs0 + i]);
       rs[1] = uni(g.rowptr[v[1]]);
       rd[1] = uni(g.rowptr[v[1] + 1]) - rs[1];
       const Split none{nullptr, nullptr, 0, INF, 0};
-      mat_level<K, 2, false, false, false>(g, plan, M, v, rs, rd, 0u, i, acc, none);
+      mat_level<K, 2, false, false, false>(g, plan, M, v, rs, rd, 0u, acc, none);
     }
   }
 }
@@ -2148,6 +2356,17 @@ static gz_status scratch_address(unsigned long long** out) {
   return GZ_OK;
 }
 
+// The last loop's evaluation choices of a count call, from the environment
+// (defaults otherwise); none of them changes a result.
+void plan_knobs(Plan& plan) {
+  plan.ie_force = env_flag("GZ_IE_FORCE");
+  plan.long_min = env_int("GZ_LONG_MIN", 256, 1, 1 << 30);
+  plan.merge_ratio = env_int("GZ_MERGE_RATIO", 4, 0, 1 << 20);
+  plan.ie_ratio = env_int("GZ_IE_RATIO", 12, 0, 1 << 20);
+  plan.sweep_min = env_int("GZ_SWEEP_MIN", 16384, 0, INT32_MAX);
+  plan.sweep_ie = env_int("GZ_SWEEP_IE", 2, 0, 1 << 20);
+}
+
 // gz_count without any device allocation: the generic kernels over every
 // root with the graph's task list from load time, the hub bitmaps only if a
 // count has already built them, and no two-phase split (its record list is
@@ -2155,10 +2374,7 @@ static gz_status scratch_address(unsigned long long** out) {
 gz_status run_count_noalloc(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                             unsigned __int128* total) {
   Plan plan = s->plan;
-  plan.ie_force = env_flag("GZ_IE_FORCE");
-  plan.long_min = env_int("GZ_LONG_MIN", 256, 1, 1 << 30);
-  plan.merge_ratio = env_int("GZ_MERGE_RATIO", 4, 0, 1 << 20);
-  plan.ie_ratio = env_int("GZ_IE_RATIO", 12, 0, 1 << 20);
+  plan_knobs(plan);
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
   const int chunk = plan.k == 3 ? 64 : 16;
@@ -2211,10 +2427,7 @@ gz_status run_count(const gz_graph* g, const gz_schedule* s, hipStream_t st,
                     bool instr, unsigned __int128* total, unsigned __int128* bytes,
                     float* kernel_ms, bool clique_ops) {
   Plan plan = s->plan;
-  plan.ie_force = env_flag("GZ_IE_FORCE");
-  plan.long_min = env_int("GZ_LONG_MIN", 256, 1, 1 << 30);
-  plan.merge_ratio = env_int("GZ_MERGE_RATIO", 4, 0, 1 << 20);
-  plan.ie_ratio = env_int("GZ_IE_RATIO", 12, 0, 1 << 20);
+  plan_knobs(plan);
   const HostGraph& h = g->host;
   const bool bounded1 = plan.lv[1].bound == 0;
   const int chunk = chunk_for(plan.k);

@@ -12,7 +12,15 @@ bit-exact against the oracle, in total and per root.
 Last-loop items whose walk reaches GZ_LONG_MIN elements are counted by the
 whole wave, merging probe lists up to GZ_MERGE_RATIO times the walk's length
 through an LDS window and probing longer ones per element; both are forced
-to their extremes here (every item long; every list merged, or none)."""
+to their extremes here (every item long; every list merged, or none).
+
+Groups of last-loop items that walk their own rows may instead be swept: the
+earlier loops' lists become one LDS bit mask per block of 2^15 vertex ids
+(hub bitmaps ANDed, negative lists without a bitmap clearing their entries).
+GZ_SWEEP_MIN=1 sweeps every eligible group; a copy of the test graph with its
+ids spread over 150,000 (no degree reindex) makes the rows span several
+blocks, with hub and non-hub lists, split and unsplit loops, and either
+choice against inclusion-exclusion (GZ_SWEEP_IE)."""
 
 import os
 import sys
@@ -27,7 +35,7 @@ from paper_1911_12877_amd import gz, synth
 pytestmark = pytest.mark.gpu
 
 ENV = ("GZ_HUB_MIN_DEG", "GZ_HUB_MAX_KB", "GZ_SPLIT_MIN_LEN", "GZ_IE_FORCE", "GZ_LONG_MIN",
-       "GZ_MERGE_RATIO")
+       "GZ_MERGE_RATIO", "GZ_SWEEP_MIN", "GZ_SWEEP_IE")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -199,3 +207,85 @@ def test_long_walks_per_root(nm):
     with _env(GZ_LONG_MIN=8, GZ_MERGE_RATIO=3, GZ_HUB_MIN_DEG=16):
         got = gz.count_roots(G, s, roots)
     assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ sweep
+
+SWEEP = [  # (hub threshold, hub cap KiB, sweep_ie, extra)
+    (1, None, 1 << 20, {}),
+    (1, None, 0, {}),
+    (8, None, 8, {"GZ_SPLIT_MIN_LEN": 0}),
+    (1, 0, 1 << 20, {}),
+    (1, 1, 8, {"GZ_LONG_MIN": 1}),
+]
+
+
+@pytest.mark.parametrize("setting", SWEEP)
+def test_sweep_one_block(cl_case, setting):
+    G, _, want = cl_case
+    hub, cap, ie, extra = setting
+    kv = dict(GZ_SWEEP_MIN=1, GZ_SWEEP_IE=ie, GZ_HUB_MIN_DEG=hub, **extra)
+    if cap is not None:
+        kv["GZ_HUB_MAX_KB"] = cap
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        with _env(**kv):
+            _say("sweep", setting, nm, induced)
+            got = gz.count(G, s)
+        assert got == want[(nm, induced)], (nm, induced, setting)
+
+
+SPREAD_N = 150000
+
+
+def spread_edges(seed=71):
+    """The Chung-Lu test graph relabelled: its 32 highest-degree vertices at
+    ids 0..31 (the leading run that gets bitmaps), the others at seeded
+    random ids up to SPREAD_N, in no degree order."""
+    src, dst, n = synth.chung_lu_edges(1500, 2.2, 10.0, seed, cap=False)
+    deg = np.bincount(np.concatenate([src, dst]), minlength=n)
+    by_deg = np.argsort(-deg, kind="stable")
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    rest = rng.choice(np.arange(32, SPREAD_N), size=n - 32, replace=False)
+    new = np.empty(n, dtype=np.int64)
+    new[by_deg[:32]] = np.arange(32)
+    new[by_deg[32:]] = rest
+    return new[src].astype(np.int32), new[dst].astype(np.int32), SPREAD_N
+
+
+@pytest.fixture(scope="module")
+def spread_case(cl_case):
+    _, _, want = cl_case  # totals do not depend on the labels
+    e = spread_edges()
+    G = gz.load_edges(*e, flags=gz.GRAPH_NO_REINDEX)
+    return G, e, want
+
+
+@pytest.mark.parametrize("setting", SWEEP)
+def test_sweep_several_blocks(spread_case, setting):
+    G, _, want = spread_case
+    hub, cap, ie, extra = setting
+    kv = dict(GZ_SWEEP_MIN=1, GZ_SWEEP_IE=ie, GZ_HUB_MIN_DEG=hub, **extra)
+    if cap is not None:
+        kv["GZ_HUB_MAX_KB"] = cap
+    for nm, induced in PATS:
+        s = gz.compile_pattern(P.named(nm), induced)
+        with _env(**kv):
+            _say("sweep spread", setting, nm, induced)
+            got = gz.count(G, s)
+        assert got == want[(nm, induced)], (nm, induced, setting)
+
+
+@pytest.mark.parametrize("nm", ["tailed_triangle", "c4", "diamond", "house"])
+def test_sweep_several_blocks_per_root(spread_case, nm):
+    G, e, _ = spread_case
+    O = oracle.from_edge_tuple(e, reindex_by_degree=False)
+    pat = P.named(nm)
+    s = gz.compile_pattern(pat, True)
+    roots = np.unique(np.concatenate([e[0], e[1]])).astype(np.int32)
+    total, want = oracle.count(O, pat, True, order=s.info()["order"], relations="thm2",
+                               roots=roots, per_root=True)
+    with _env(GZ_SWEEP_MIN=1, GZ_HUB_MIN_DEG=1):
+        got = gz.count_roots(G, s, roots)
+    assert np.array_equal(got, want)
+    assert int(got.astype(object).sum()) == total
