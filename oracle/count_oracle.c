@@ -150,20 +150,33 @@ static int64_t prefix_len(const search_t* s, int32_t u, int64_t b) {
  * below the position's bound: 4 bytes each, plus 8 bytes for the list's two
  * row offsets.  When the position extends the candidate set of position i-1
  * (see extension_rule) it reads instead that set's elements below m[i-1]
- * (their number is m[i-1]'s rank in it) and only the lists it adds. */
-static void add_level_bytes(search_t* s, int i) {
-    int64_t b = (s->bound[i] >= 0) ? (int64_t)s->m[s->bound[i]] : INT64_MAX;
-    if (s->extends[i]) {
-        s->bytes += (u128)(4 * (int64_t)s->rank[i - 1]);
-        for (int j = 0; j < i; ++j)
-            if (s->added[i][j]) s->bytes += (u128)(4 * prefix_len(s, s->m[j], b) + 8);
-        return;
-    }
-    for (int j = 0; j < i; ++j) {
-        if (s->black[i][j] || s->induced) {
-            s->bytes += (u128)(4 * prefix_len(s, s->m[j], b) + 8);
-        }
-    }
+ * (their number is m[i-1]'s rank in it) and only the lists it adds.
+ *
+ * Position i is evaluated once per iteration of position i-1's loop, and
+ * only N(m[i-1]) changes along that loop: the other operands (the lists of
+ * positions before i-1, the extended set) are read once per execution of
+ * the loop.  level_bytes_varying counts the per-iteration part (called on
+ * entering position i); level_bytes_invariant the rest, once, after position
+ * i-1's loop, with m[i-1] and rank[i-1] of its last iteration (the longest
+ * cut). */
+static int64_t level_cut(const search_t* s, int i) {
+    return (s->bound[i] >= 0) ? (int64_t)s->m[s->bound[i]] : INT64_MAX;
+}
+
+static int level_reads(const search_t* s, int i, int j) {
+    return s->extends[i] ? s->added[i][j] : (s->black[i][j] || s->induced);
+}
+
+static void level_bytes_varying(search_t* s, int i) {
+    if (level_reads(s, i, i - 1))
+        s->bytes += (u128)(4 * prefix_len(s, s->m[i - 1], level_cut(s, i)) + 8);
+}
+
+static void level_bytes_invariant(search_t* s, int i) {
+    int64_t b = level_cut(s, i);
+    if (s->extends[i]) s->bytes += (u128)(4 * (int64_t)s->rank[i - 1]);
+    for (int j = 0; j < i - 1; ++j)
+        if (level_reads(s, i, j)) s->bytes += (u128)(4 * prefix_len(s, s->m[j], b) + 8);
 }
 
 /* Position i (3 <= i <= k-1) extends position i-1's candidate set when it is
@@ -193,7 +206,7 @@ static void extension_rule(search_t* s) {
 }
 
 static void dfs(search_t* s, int i) {
-    if (s->instrument) add_level_bytes(s, i);
+    if (s->instrument) level_bytes_varying(s, i);
     /* source list: the earlier black neighbour of smallest degree */
     int src = -1;
     int64_t best = INT64_MAX;
@@ -207,7 +220,7 @@ static void dfs(search_t* s, int i) {
     for (int a = 0; a < i; ++a)
         if (s->upper[i][a] && s->m[a] < ub) ub = s->m[a];
     int32_t u = s->m[src];
-    int32_t accepted = 0;
+    int32_t accepted = 0, last = 0;
     for (int64_t e = s->rowptr[u]; e < s->rowptr[u + 1]; ++e) {
         int32_t x = s->col[e];
         if (x >= ub) break;
@@ -226,7 +239,13 @@ static void dfs(search_t* s, int i) {
             s->rank[i] = accepted;
             dfs(s, i + 1);
         }
+        last = x;
         ++accepted;
+    }
+    if (s->instrument && i < s->k - 1 && accepted > 0) {
+        s->m[i] = last;
+        s->rank[i] = accepted - 1;
+        level_bytes_invariant(s, i + 1);
     }
 }
 
@@ -281,8 +300,8 @@ int oracle_count(int32_t n, const int64_t* rowptr, const int32_t* col,
 }
 
 /* Algorithmic bytes of the schedule's bounded set operations (see
- * add_level_bytes) summed over every evaluation of positions 1..k-1 reached
- * from the given roots.  bound[i] is the single kept restriction of
+ * level_bytes_varying, level_bytes_invariant) summed over every evaluation
+ * of positions 1..k-1 reached from the given roots.  bound[i] is the single kept restriction of
  * position i (Theorem 2), -1 for none; the enumeration itself is restricted
  * by exactly these bounds. */
 int oracle_instrument(int32_t n, const int64_t* rowptr, const int32_t* col,

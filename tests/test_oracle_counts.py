@@ -265,11 +265,24 @@ def test_per_root_decomposition():
     assert t2 == total == int(per.sum())
 
 
+# The algorithmic bytes, by definition: loop i is evaluated once per
+# iteration of loop i-1 and reads, for each list of its set expression
+# (pattern neighbours intersected, non-neighbours subtracted in induced
+# mode), the part below the loop's bound (4 B per element) and the row's two
+# offsets (8 B).  Only N(v_{i-1}) changes along loop i-1: it is read per
+# iteration, the other lists once per execution of loop i-1 that has an
+# iteration, cut at its last (largest) iteration's bound.  A loop that
+# extends loop i-1's set reads that set's elements below v_{i-1} instead of
+# the shared lists (once per execution: up to the last iteration, i.e. the
+# set's size less one) and the lists it adds.
+
+
 def test_instrument_clique_extension_closed_form():
-    """K4, identity schedule, bounds v1<v0, v2<v1, v3<v2: loops 1 and 2 read
-    their lists below the bound; loop 3 extends loop 2's set C2 = N(v0) ∩
-    N(v1) ∩ [0, v1), reading the elements of C2 below v2 (v2's rank in C2)
-    and the part of N(v2) below v2."""
+    """K4, identity schedule, bounds v1<v0, v2<v1, v3<v2.  Loop 1: N(v0)
+    below v0.  Loop 2: N(v1) below v1 per v1, and once per root N(v0) below
+    its last v1 (lo(v0) - 1 elements).  Loop 3 extends loop 2's set
+    C2 = N(v0) ∩ N(v1) ∩ [0, v1): the part of N(v2) below v2 per v2, and
+    once per (v0, v1) the elements of C2 below its last element."""
     e = synth.chung_lu_edges(300, 2.3, 12.0, 72, cap=True)
     g = oracle.from_edge_tuple(e)
     lo = oracle.lo_end(g)
@@ -277,11 +290,15 @@ def test_instrument_clique_extension_closed_form():
     want = int(np.sum(4 * lo + 8))
     for v0 in range(g.n):
         row0 = g.col[g.rowptr[v0]:g.rowptr[v0 + 1]]
+        if lo[v0] > 0:
+            want += 4 * int(lo[v0] - 1) + 8
         for v1 in row0[row0 < v0]:
-            want += 4 * int(np.sum(row0 < v1)) + 4 * int(lo[v1]) + 16
+            want += 4 * int(lo[v1]) + 8
             c2 = sorted(x for x in nb[v0] & nb[v1] if x < v1)
-            for rank, v2 in enumerate(c2):
-                want += 4 * rank + 4 * int(lo[v2]) + 8
+            if c2:
+                want += 4 * (len(c2) - 1)
+            for v2 in c2:
+                want += 4 * int(lo[v2]) + 8
     k4 = P.named("k4")
     b, c = oracle.instrument(g, k4, True, (0, 1, 2, 3), [-1, 0, 1, 2])
     assert b == want
@@ -290,16 +307,18 @@ def test_instrument_clique_extension_closed_form():
 
 def test_instrument_triangle_closed_form():
     """Triangle, schedule (0,1,2), bounds v1<v0, v2<v1: level 1 reads the
-    lower part of N(v0) once per root; level 2 reads N(v0) and N(v1) below
-    v1 once per lower edge (v0, v1)."""
+    lower part of N(v0) once per root; level 2 reads the lower part of N(v1)
+    once per lower edge (v0, v1), and N(v0) below the root's last v1 once."""
     e = synth.chung_lu_edges(300, 2.3, 10.0, 71, cap=True)
     g = oracle.from_edge_tuple(e)
     lo = oracle.lo_end(g)
     want = int(np.sum(4 * lo + 8))
     for v0 in range(g.n):
         row0 = g.col[g.rowptr[v0]:g.rowptr[v0 + 1]]
+        if lo[v0] > 0:
+            want += 4 * int(lo[v0] - 1) + 8
         for v1 in row0[row0 < v0]:
-            want += 4 * int(np.sum(row0 < v1)) + 4 * int(lo[v1]) + 16
+            want += 4 * int(lo[v1]) + 8
     tri = P.named("triangle")
     b, c = oracle.instrument(g, tri, True, (0, 1, 2), [-1, 0, 1])
     assert b == want
@@ -308,13 +327,12 @@ def test_instrument_triangle_closed_form():
 
 def test_instrument_induced_c4_by_definition():
     """Induced 4-cycle 0-1-2-3-0, schedule (0, 1, 3, 2), bounds v1 < v0,
-    v2 < v1, v3 < v0, counted from the definition of the algorithmic bytes:
-    every evaluation of loop i reads, for each list of its set expression
-    (pattern neighbours intersected, non-neighbours subtracted), the part
-    below the loop's bound (4 B per element) and the row's two offsets (8 B).
-    Loop 1: N(v0) below v0.  Loop 2 (pattern vertex 3): N(v0) and N(v1)
-    below v1.  Loop 3 (pattern vertex 2): N(v0), N(v1) and N(v2) below v0.
-    No loop extends the enclosing one's set (loop 3 is bounded by loop 0)."""
+    v2 < v1, v3 < v0.  Loop 1: N(v0) below v0.  Loop 2 (pattern vertex 3,
+    N(v0) intersected, N(v1) subtracted, below v1): N(v1) per v1, N(v0) below
+    the root's last v1 once.  Loop 3 (pattern vertex 2, N(v1) and N(v2)
+    intersected, N(v0) subtracted, below v0): N(v2) per v2, N(v0) and N(v1)
+    once per (v0, v1) with a v2.  No loop extends the enclosing one's set
+    (loop 3 is bounded by loop 0)."""
     e = synth.chung_lu_edges(250, 2.3, 10.0, 73, cap=True)
     g = oracle.from_edge_tuple(e)
     nb = [g.col[g.rowptr[v]:g.rowptr[v + 1]] for v in range(g.n)]
@@ -327,12 +345,16 @@ def test_instrument_induced_c4_by_definition():
     count = 0
     for v0 in range(g.n):
         want += 4 * below(v0, v0) + 8
-        for v1 in nb[v0][nb[v0] < v0].tolist():
-            want += 4 * (below(v0, v1) + below(v1, v1)) + 16
-            for v2 in nb[v0][nb[v0] < v1].tolist():
-                if v2 in ns[v1]:
-                    continue
-                want += 4 * (below(v0, v0) + below(v1, v0) + below(v2, v0)) + 24
+        v1s = nb[v0][nb[v0] < v0].tolist()
+        if v1s:
+            want += 4 * below(v0, v1s[-1]) + 8
+        for v1 in v1s:
+            want += 4 * below(v1, v1) + 8
+            v2s = [v2 for v2 in nb[v0][nb[v0] < v1].tolist() if v2 not in ns[v1]]
+            if v2s:
+                want += 4 * (below(v0, v0) + below(v1, v0)) + 16
+            for v2 in v2s:
+                want += 4 * below(v2, v0) + 8
                 count += sum(1 for x in ns[v1] & ns[v2] if x < v0 and x not in ns[v0])
     c4 = P.named("c4")
     b, c = oracle.instrument(g, c4, True, (0, 1, 3, 2), [-1, 0, 1, 0])
@@ -343,9 +365,9 @@ def test_instrument_induced_c4_by_definition():
 def test_instrument_induced_tailed_triangle_by_definition():
     """Induced tailed triangle (triangle 0-1-2, tail 3 on 0), schedule
     (1, 2, 0, 3), one bound v1 < v0.  Loop 1: N(v0) below v0.  Loop 2
-    (pattern vertex 0, unbounded): all of N(v0) and N(v1).  Loop 3 (the tail,
-    unbounded): all of N(v2) intersected and, vertex-induced, all of N(v0)
-    and N(v1) subtracted."""
+    (pattern vertex 0, unbounded): all of N(v1) per v1, all of N(v0) once
+    per root.  Loop 3 (the tail, unbounded): all of N(v2) per v2 and,
+    vertex-induced, all of N(v0) and N(v1) once per (v0, v1) with a v2."""
     e = synth.chung_lu_edges(250, 2.3, 10.0, 74, cap=True)
     g = oracle.from_edge_tuple(e)
     nb = [g.col[g.rowptr[v]:g.rowptr[v + 1]] for v in range(g.n)]
@@ -355,10 +377,16 @@ def test_instrument_induced_tailed_triangle_by_definition():
     count = 0
     for v0 in range(g.n):
         want += 4 * int(np.sum(nb[v0] < v0)) + 8
-        for v1 in nb[v0][nb[v0] < v0].tolist():
-            want += 4 * (deg[v0] + deg[v1]) + 16
-            for v2 in sorted(ns[v0] & ns[v1]):
-                want += 4 * (deg[v0] + deg[v1] + deg[v2]) + 24
+        v1s = nb[v0][nb[v0] < v0].tolist()
+        if v1s:
+            want += 4 * deg[v0] + 8
+        for v1 in v1s:
+            want += 4 * deg[v1] + 8
+            v2s = sorted(ns[v0] & ns[v1])
+            if v2s:
+                want += 4 * (deg[v0] + deg[v1]) + 16
+            for v2 in v2s:
+                want += 4 * deg[v2] + 8
                 count += sum(1 for x in ns[v2]
                              if x not in (v0, v1) and x not in ns[v0] and x not in ns[v1])
     tt = P.named("tailed_triangle")
