@@ -58,7 +58,7 @@ constexpr int sweep_words() { return K <= SW_KMAX ? SW_WORDS : 1; }
 // choice).  Their loops wait on scattered loads, so for 4-vertex patterns
 // more resident waves beat the few registers spilled to reach them.
 template <int K>
-constexpr int mine_waves() { return K == 4 ? 4 : 1; }
+constexpr int mine_waves() { return K == 4 ? 5 : 1; }
 template <int K>
 constexpr int heavy_waves() { return K == 4 ? 7 : 1; }
 
@@ -317,7 +317,7 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t x) {
 // no item reaches are skipped.  Within a block the items' runs are read a
 // tile of 64 consecutive entries at a time, up to SW_TILES tiles of
 // different items in flight.  The result is wave-uniform.
-constexpr int SW_TILES = 4;
+constexpr int SW_TILES = 8;
 template <int K>
 __device__ long long sweep_items(const Graph& g, WaveMem<K>& M, const int32_t (&v)[K],
                                  const int32_t (&rs)[K], const int32_t (&rd)[K], uint32_t pm,
