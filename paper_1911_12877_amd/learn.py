@@ -25,14 +25,13 @@ Command line (GPU):  python -m paper_1911_12877_amd.learn collect OUT.npz
 
 from __future__ import annotations
 
-import itertools
 import os
 import sys
 import time
 
 import numpy as np
 
-from . import gz, synth
+from . import gz, motifs, synth
 
 H_DEFAULT = 128
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models",
@@ -61,16 +60,9 @@ def _connected(a):
 
 
 def canonical(a):
-    """Largest upper-triangle bit string over all relabellings."""
-    k = a.shape[0]
-    best = -1
-    for p in itertools.permutations(range(k)):
-        c = 0
-        for i in range(k):
-            for j in range(i + 1, k):
-                c = (c << 1) | int(a[p[i], p[j]])
-        best = max(best, c)
-    return best
+    """Canonical code of a pattern (largest upper-triangle bit string over
+    all relabellings), as the census computes it."""
+    return motifs.canonical_code(a)
 
 
 def held_out_patterns():
@@ -86,16 +78,9 @@ def held_out_patterns():
 
 
 def connected_patterns(k):
-    pairs = [(i, j) for i in range(k) for j in range(i + 1, k)]
-    seen = {}
-    for mask in range(1 << len(pairs)):
-        a = _edges_adj(k, [pairs[b] for b in range(len(pairs)) if mask >> b & 1])
-        if not _connected(a):
-            continue
-        c = canonical(a)
-        if c not in seen:
-            seen[c] = a
-    return [seen[c] for c in sorted(seen)]
+    """The connected k-vertex patterns in canonical-code order (the corpus's
+    order)."""
+    return sorted(motifs.connected_patterns(k), key=motifs.canonical_code)
 
 
 def random_patterns(k, count, seed, exclude_codes, min_edges=0):
