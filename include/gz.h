@@ -191,8 +191,8 @@ void gz_free_schedule(gz_schedule* s);
  *    recorded by the first launch (up to the capacity; later ones are
  *    expanded in place) and expanded in 256-element pieces by a second, the
  *    host reading the record count in between.
- *  - GZ_HUB_MIN_DEG (>= 1, default 1024) and GZ_HUB_MAX_KB (KiB, 0 turns
- *    them off, default 8 GiB): the leading vertices of at least that degree
+ *  - GZ_HUB_MIN_DEG (>= 1, default 512) and GZ_HUB_MAX_KB (KiB, 0 turns
+ *    them off, default 32 GiB): the leading vertices of at least that degree
  *    get a dense neighbour bitmap, built on the first count that asks for
  *    it and kept with the graph; membership probes into their lists read
  *    one bit.

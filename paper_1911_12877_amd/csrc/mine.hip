@@ -1869,7 +1869,7 @@ int hub_min_deg() {
     const long v = std::strtol(e, &end, 10);
     if (end && *end == '\0' && v >= 1 && v <= INT32_MAX) return (int)v;
   }
-  return 1024;
+  return 512;
 }
 
 // Bytes all bitmaps of one graph may take (GZ_HUB_MAX_KB overrides, in KiB;
@@ -1881,7 +1881,7 @@ long long hub_cap_bytes() {
     const long long v = std::strtoll(e, &end, 10);
     if (end && *end == '\0' && v >= 0 && v <= (1ll << 40)) return v << 10;
   }
-  return 8ll << 30;
+  return 32ll << 30;
 }
 
 // The graph's hub bitmaps for the current settings, built on first use and
