@@ -99,6 +99,37 @@ def test_rmat20_cliques(rmat20, k):
         assert total == int(json.load(f)["counts"][f"k{k}"])
 
 
+def test_rmat20_four_vertex_totals_identities(rmat20):
+    """Full counts on R-MAT scale 20 tied together by identities that hold
+    for any graph: every copy of a 4-vertex pattern P (edge-induced count
+    N_P) spans 4 vertices whose induced subgraph contains P, and each
+    connected 4-vertex graph contains a fixed number of copies of P (the
+    4-cycle: one in the diamond, three in K4; the diamond: six in K4; the
+    tailed triangle: four in the diamond, twelve in K4).  So
+    N_c4 = I_c4 + I_diamond + 3 K4, N_diamond = I_diamond + 6 K4 and
+    N_tt = I_tt + 4 I_diamond + 12 K4, with I the vertex-induced counts.
+    The two sides come from different plans and kernels (negative lists,
+    inclusion-exclusion and the swept last loop in induced mode, positive
+    lists only in edge-induced mode, the bit-row clique path for K4), so a
+    mistake in one of them breaks an identity at the full size."""
+    G, O = rmat20
+    cnt = {}
+    for nm in ("c4", "diamond", "tailed_triangle"):
+        for induced in (True, False):
+            cnt[(nm, induced)] = gz.count(G, gz.compile_pattern(P.named(nm), induced))
+            _say("rmat20", nm, "induced" if induced else "edge-induced", cnt[(nm, induced)])
+    k4 = gz.count(G, gz.compile_pattern(P.named("k4"), True))
+    I = {nm: cnt[(nm, True)] for nm in ("c4", "diamond", "tailed_triangle")}
+    N = {nm: cnt[(nm, False)] for nm in ("c4", "diamond", "tailed_triangle")}
+    assert N["c4"] == I["c4"] + I["diamond"] + 3 * k4
+    assert N["diamond"] == I["diamond"] + 6 * k4
+    assert N["tailed_triangle"] == I["tailed_triangle"] + 4 * I["diamond"] + 12 * k4
+    # K4 itself is pinned by the oracle's stored total
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "rmat20_clique_totals.json")) as f:
+        assert k4 == int(json.load(f)["counts"]["k4"])
+
+
 @pytest.mark.parametrize("k", [4, 5])
 def test_rmat20_cliques_stored_roots(rmat20, k):
     """K4/K5 per-root counts against the oracle's stored values at roots
