@@ -213,6 +213,26 @@ def test_rmat22_induced_patterns(rmat22, nm):
     _learned_parity(G, O, "rmat22", nm, adj, s, 220 + len(nm))
 
 
+@pytest.mark.skipif(os.environ.get("GZ_FULL_TOTALS") != "1",
+                    reason="full R-MAT 22 counts take about four minutes of GPU time; "
+                           "set GZ_FULL_TOTALS=1 to run")
+def test_rmat22_four_vertex_totals_identities(rmat22):
+    """The benchmark's full induced totals on R-MAT scale 22 (4-cycle,
+    diamond, tailed triangle) against the edge-induced ones and K4 through
+    the same containment identities as on R-MAT 20."""
+    G, _ = rmat22
+    I, N = {}, {}
+    for nm in ("c4", "diamond", "tailed_triangle"):
+        I[nm] = gz.count(G, gz.compile_pattern(P.named(nm), True))
+        N[nm] = gz.count(G, gz.compile_pattern(P.named(nm), False))
+        _say("rmat22", nm, "induced", I[nm], "edge-induced", N[nm])
+    k4 = gz.count(G, gz.compile_pattern(P.named("k4"), True))
+    _say("rmat22 k4", k4)
+    assert N["c4"] == I["c4"] + I["diamond"] + 3 * k4
+    assert N["diamond"] == I["diamond"] + 6 * k4
+    assert N["tailed_triangle"] == I["tailed_triangle"] + 4 * I["diamond"] + 12 * k4
+
+
 @pytest.fixture(scope="module")
 def learned_graphs():
     out = {}
